@@ -1,0 +1,28 @@
+"""Build the CPU oracle library (test infrastructure).
+
+gcc, -O2, no floating-point contraction, no fast-math, glibc libm, single
+threaded: every double operation in the oracle rounds once, in source order.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "pagani_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+CFLAGS = ["-O2", "-std=c99", "-D_GNU_SOURCE", "-ffp-contract=off",
+          "-fno-fast-math", "-Wall", "-Wextra", "-shared", "-fPIC"]
+
+
+def build(verbose: bool = False) -> str:
+    tmp = LIB + ".tmp"
+    cmd = ["gcc", *CFLAGS, "-o", tmp, SRC, "-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

@@ -1,0 +1,785 @@
+/*
+ * pagani_oracle.c -- CPU reference ("oracle") for the PAGANI integrator.
+ *
+ * TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT. Only the test suite, the
+ * smoke check and the benchmark's CPU-baseline leg may load this library.
+ * It is a plain, slow, sequential, single-threaded implementation of one
+ * PAGANI run (Sakiotis et al., "PAGANI: A Parallel Adaptive GPU Algorithm
+ * for Numerical Integration", SC'21): the main loop of Algorithm 2
+ * (Section 3.1) and the threshold search of Algorithm 3 (Section 3.5.3).
+ * It shares no code, header, table or helper with the GPU library.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC (glibc libm).
+ * All floating point is IEEE binary64 without contraction, so every
+ * operation below rounds exactly once in the order written.
+ *
+ * Readings where the paper is silent or garbled (each is listed, with its
+ * justification, in the design notes of the repository):
+ *   R1  cubature: the degree-7 Genz-Malik fully symmetric rule with its
+ *       embedded degree-5 rule (Section 2.1 and 3.2 name the Genz-Malik
+ *       rules but print neither points nor weights);
+ *   R2  raw error: |R7 - R5|, the degree-5 null rule of the same points;
+ *   R3  split axis: argmax of the fourth divided difference along each axis,
+ *       ties (within a relative 1e-10 of the maximum, or within 1e-12 of
+ *       the magnitude of the f values that enter the differences, which is
+ *       rounding noise) broken by the widest axis, then the lowest index;
+ *   R4  two-level error (Section 3.2): for siblings a, b with parent
+ *       estimate Vp, delta = |Va + Vb - Vp| / 4, S = Ea + Eb,
+ *       E <- E (1 + 2 delta / S) + delta (E + delta when S = 0);
+ *   R5  classification (Section 3.5.1, Lemma 1): finished iff E <= tau |V|;
+ *   R6  threshold search (Algorithm 3) with the directions fixed by the
+ *       Figure 3 narrative, the accuracy requirement measured against the
+ *       error finished regions may still carry, P_max relaxed only under
+ *       memory pressure, 10 direction changes / 64 trials at most;
+ *   R7  filter/split order: stable compaction; children of the j-th active
+ *       region go to j (lower half) and j + n_active (upper half).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#include <time.h>
+
+#define OR_DMAX 16
+
+enum { OR_PRODUCT_PEAK = 0, OR_GAUSSIAN = 1, OR_OSCILLATORY = 2,
+       OR_CORNER_PEAK = 3, OR_MONOMIAL = 4 };
+
+enum { OR_OK = 0, OR_MAX_ITERS = 1, OR_MEMORY_EXHAUSTED = 2,
+       OR_NO_ACTIVE = 3, OR_EINVAL = -1, OR_ENOMEM = -2, OR_EREPLAY = -5 };
+
+/* ------------------------------------------------------------------------
+ * Integrands (Section 4.1 uses members of these families; the workloads
+ * draw their parameters at random).
+ * ---------------------------------------------------------------------- */
+double oracle_f(int family, int d, const double *p, const double *x)
+{
+    int i;
+    double s, r;
+    switch (family) {
+    case OR_PRODUCT_PEAK:            /* prod 1 / (a^-2 + (x - u)^2) */
+        r = 1.0;
+        for (i = 0; i < d; i++) {
+            double a = p[i], u = p[d + i];
+            r = r * (1.0 / (1.0 / (a * a) + (x[i] - u) * (x[i] - u)));
+        }
+        return r;
+    case OR_GAUSSIAN:                /* exp(-sum a^2 (x - u)^2) */
+        s = 0.0;
+        for (i = 0; i < d; i++) {
+            double a = p[i], u = p[d + i];
+            s = s + a * a * ((x[i] - u) * (x[i] - u));
+        }
+        return exp(-s);
+    case OR_OSCILLATORY:             /* cos(2 pi u_1 + sum a x) */
+        s = 2.0 * M_PI * p[d];
+        for (i = 0; i < d; i++)
+            s = s + p[i] * x[i];
+        return cos(s);
+    case OR_CORNER_PEAK:             /* (1 + sum a x)^-(d+1) */
+        s = 1.0;
+        for (i = 0; i < d; i++)
+            s = s + p[i] * x[i];
+        return pow(s, -(double)(d + 1));
+    case OR_MONOMIAL:                /* prod x^alpha */
+        r = 1.0;
+        for (i = 0; i < d; i++) {
+            int k, e = (int)p[i];
+            for (k = 0; k < e; k++)
+                r = r * x[i];
+        }
+        return r;
+    default:
+        return NAN;
+    }
+}
+
+/* ------------------------------------------------------------------------
+ * Cubature rule (reading R1). Fully symmetric points on [-1,1]^d:
+ *   orbit 1: the centre                                      (1 point)
+ *   orbit 2: +-lambda2 e_i                                   (2d points)
+ *   orbit 3: +-lambda3 e_i                                   (2d points)
+ *   orbit 4: +-lambda4 e_i +-lambda4 e_j, i < j              (2d(d-1))
+ *   orbit 5: lambda5 (+-1, ..., +-1)                         (2^d points)
+ * lambda2^2 = 9/70, lambda3^2 = lambda4^2 = 9/10, lambda5^2 = 9/19.
+ * Weights are per point and relative to the box volume (they sum to 1).
+ * ---------------------------------------------------------------------- */
+long oracle_npoints(int d)
+{
+    return (1L << d) + 2L * d * d + 2L * d + 1L;
+}
+
+void oracle_rule(int d, double w7[5], double w5[5], double lambda[5])
+{
+    double D = 19683.0;             /* 3^9 */
+    w7[0] = (12824.0 - 9120.0 * d + 400.0 * d * d) / D;
+    w7[1] = 980.0 / 6561.0;
+    w7[2] = (1820.0 - 400.0 * d) / D;
+    w7[3] = 200.0 / D;
+    w7[4] = 6859.0 / D / ldexp(1.0, d);
+    w5[0] = (729.0 - 950.0 * d + 50.0 * d * d) / 729.0;
+    w5[1] = 245.0 / 486.0;
+    w5[2] = (265.0 - 100.0 * d) / 1458.0;
+    w5[3] = 25.0 / 729.0;
+    w5[4] = 0.0;
+    lambda[0] = 0.0;
+    lambda[1] = sqrt(9.0 / 70.0);
+    lambda[2] = sqrt(9.0 / 10.0);
+    lambda[3] = sqrt(9.0 / 10.0);
+    lambda[4] = sqrt(9.0 / 19.0);
+}
+
+/* Fourth-difference tie band of reading R3: relative band and the noise
+   allowance relative to the magnitude of the values entering a difference. */
+#define OR_AXIS_TIE 1e-10
+#define OR_AXIS_NOISE 1e-12
+#define OR_FLOOR_ULPS 256.0
+
+/*
+ * Evaluate one region (the EVALUATE step of Algorithm 2, Section 3.2):
+ * integral estimate V (degree-7 rule), raw error E = |R7 - R5| (reading
+ * R2), split axis K (reading R3) and, for parity checks, the per-axis
+ * fourth differences Dout[d] and the rounding floors of V and E:
+ *   floorV = 256 eps vol sum_p |w7(p)| |f(x_p)|,
+ *   floorE = 256 eps vol sum_p |w7(p) - w5(p)| |f(x_p)|,
+ * 256 ulps of the absolute weighted sums: room for the few-ulp differences
+ * between two libm implementations, amplified by the integrand's
+ * conditioning, that survive the weighted sum when it cancels.
+ * The region is the box [lo, lo + w].
+ */
+static void eval_region(int family, int d, const double *par,
+                        const double *lo, const double *w,
+                        const double w7[5], const double w5[5],
+                        const double lam[5],
+                        double *V, double *E, int *K, double *Dout,
+                        double *floorV, double *floorE, double *floorD)
+{
+    double c[OR_DMAX], h[OR_DMAX], x[OR_DMAX];
+    double S[5] = {0, 0, 0, 0, 0};        /* orbit sums */
+    double A[5] = {0, 0, 0, 0, 0};        /* orbit sums of |f| */
+    double P2[OR_DMAX], P3[OR_DMAX], Dd[OR_DMAX], Q2[OR_DMAX], Q3[OR_DMAX];
+    double vol = 1.0, fc, f, sum7, sumN, fl7, flN, dmax, nmax;
+    int i, j, k, si, sj, best;
+    long b;
+
+    for (i = 0; i < d; i++) {
+        h[i] = w[i] * 0.5;
+        c[i] = lo[i] + h[i];
+        vol = vol * w[i];
+    }
+
+    /* orbit 1: centre */
+    for (k = 0; k < d; k++) x[k] = c[k];
+    fc = oracle_f(family, d, par, x);
+    S[0] = fc;
+    A[0] = fabs(fc);
+
+    /* orbits 2 and 3: along each axis, + then - */
+    for (i = 0; i < d; i++) {
+        int o;
+        for (o = 1; o <= 2; o++) {
+            double pair = 0.0, apair = 0.0;
+            for (si = 0; si < 2; si++) {
+                double sg = si == 0 ? 1.0 : -1.0;
+                for (k = 0; k < d; k++) x[k] = c[k];
+                x[i] = c[i] + sg * (lam[o] * h[i]);
+                f = oracle_f(family, d, par, x);
+                S[o] = S[o] + f;
+                A[o] = A[o] + fabs(f);
+                pair = pair + f;
+                apair = apair + fabs(f);
+            }
+            if (o == 1) { P2[i] = pair; Q2[i] = apair; }
+            else { P3[i] = pair; Q3[i] = apair; }
+        }
+    }
+
+    /* orbit 4: pairs of axes, four sign choices each */
+    for (i = 0; i < d; i++)
+        for (j = i + 1; j < d; j++)
+            for (si = 0; si < 2; si++)
+                for (sj = 0; sj < 2; sj++) {
+                    for (k = 0; k < d; k++) x[k] = c[k];
+                    x[i] = c[i] + (si == 0 ? 1.0 : -1.0) * (lam[3] * h[i]);
+                    x[j] = c[j] + (sj == 0 ? 1.0 : -1.0) * (lam[3] * h[j]);
+                    f = oracle_f(family, d, par, x);
+                    S[3] = S[3] + f;
+                    A[3] = A[3] + fabs(f);
+                }
+
+    /* orbit 5: all 2^d sign vectors; bit k of b set means the - sign */
+    for (b = 0; b < (1L << d); b++) {
+        for (k = 0; k < d; k++)
+            x[k] = c[k] + (((b >> k) & 1) ? -1.0 : 1.0) * (lam[4] * h[k]);
+        f = oracle_f(family, d, par, x);
+        S[4] = S[4] + f;
+        A[4] = A[4] + fabs(f);
+    }
+
+    sum7 = 0.0; sumN = 0.0; fl7 = 0.0; flN = 0.0;
+    for (k = 0; k < 5; k++) {
+        sum7 = sum7 + w7[k] * S[k];
+        sumN = sumN + (w7[k] - w5[k]) * S[k];
+        fl7 = fl7 + fabs(w7[k]) * A[k];
+        flN = flN + fabs(w7[k] - w5[k]) * A[k];
+    }
+    *V = vol * sum7;
+    *E = fabs(vol * sumN);
+    *floorV = OR_FLOOR_ULPS * 2.220446049250313e-16 * vol * fl7;
+    *floorE = OR_FLOOR_ULPS * 2.220446049250313e-16 * vol * flN;
+
+    /* split axis: fourth divided difference, lambda2^2 / lambda3^2 = 1/7 */
+    dmax = 0.0;
+    nmax = 0.0;
+    for (i = 0; i < d; i++) {
+        double nm;
+        Dd[i] = fabs((P2[i] - 2.0 * fc) - (P3[i] - 2.0 * fc) / 7.0);
+        if (Dd[i] > dmax) dmax = Dd[i];
+        /* absolute size of the values that enter D_i */
+        nm = Q2[i] + Q3[i] / 7.0 + (12.0 / 7.0) * fabs(fc);
+        if (nm > nmax) nmax = nm;
+    }
+    /* tied with the maximum: within a relative 1e-10 of it, or within the
+       noise allowance 1e-12 * nmax (differences that small are rounding) */
+    best = -1;
+    for (i = 0; i < d; i++) {
+        if (Dd[i] >= dmax - OR_AXIS_TIE * dmax - OR_AXIS_NOISE * nmax) {
+            if (best < 0 || w[i] > w[best]) best = i;
+        }
+    }
+    if (floorD) *floorD = OR_AXIS_NOISE * nmax;
+    *K = best < 0 ? 0 : best;
+    if (Dout)
+        for (i = 0; i < d; i++) Dout[i] = Dd[i];
+}
+
+/*
+ * Evaluate n regions given as structure-of-arrays lower corners and widths
+ * (lo[k * ld + i], w[k * ld + i] for axis k of region i). Any output pointer
+ * may be NULL except V, E, K. Dout is [n][d] when given; floorD is the
+ * rounding floor of the largest fourth difference of each region.
+ */
+int oracle_eval_regions(int family, int d, const double *par, long n,
+                        const double *lo, const double *w, long ld,
+                        double *V, double *E, uint8_t *K, double *Dout,
+                        double *floorV, double *floorE, double *floorD)
+{
+    double w7[5], w5[5], lam[5], l[OR_DMAX], ww[OR_DMAX], fv, fe, fd;
+    long i;
+    int k, kk;
+    if (d < 1 || d > OR_DMAX || n < 0) return OR_EINVAL;
+    oracle_rule(d, w7, w5, lam);
+    for (i = 0; i < n; i++) {
+        for (k = 0; k < d; k++) {
+            l[k] = lo[k * ld + i];
+            ww[k] = w[k * ld + i];
+        }
+        eval_region(family, d, par, l, ww, w7, w5, lam, &V[i], &E[i], &kk,
+                    Dout ? Dout + i * d : NULL, &fv, &fe, &fd);
+        K[i] = (uint8_t)kk;
+        if (floorV) floorV[i] = fv;
+        if (floorE) floorE[i] = fe;
+        if (floorD) floorD[i] = fd;
+    }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * TWO-LEVEL-ERROR (Section 3.2, reading R4). The list holds 2*npairs
+ * regions; region i and region i + npairs are the two halves of the parent
+ * whose estimate is Vp[i]. E is refined in place.
+ * ---------------------------------------------------------------------- */
+void oracle_two_level(long npairs, const double *V, double *E,
+                      const double *Vp)
+{
+    long i;
+    for (i = 0; i < npairs; i++) {
+        long a = i, b = i + npairs;
+        double delta = fabs(V[a] + V[b] - Vp[i]) / 4.0;
+        double S = E[a] + E[b];
+        if (S > 0.0) {
+            double g = 1.0 + 2.0 * delta / S;
+            E[a] = E[a] * g + delta;
+            E[b] = E[b] * g + delta;
+        } else {
+            E[a] = E[a] + delta;
+            E[b] = E[b] + delta;
+        }
+    }
+}
+
+/* REL-ERR-CLASSIFY (Section 3.5.1, reading R5): A = 1 keeps a region active. */
+void oracle_classify(long n, const double *V, const double *E, double tau_rel,
+                     int relerr_filter, uint8_t *A)
+{
+    long i;
+    for (i = 0; i < n; i++)
+        A[i] = relerr_filter ? (uint8_t)(E[i] > tau_rel * fabs(V[i])) : 1;
+}
+
+/* Compensated (Neumaier) sum of x[i] * (mask ? mask[i] : 1). */
+double oracle_sum(long n, const double *x, const uint8_t *mask)
+{
+    double s = 0.0, c = 0.0, t;
+    long i;
+    for (i = 0; i < n; i++) {
+        double y = (mask && !mask[i]) ? 0.0 : x[i];
+        t = s + y;
+        if (fabs(s) >= fabs(y)) c += (s - t) + y;
+        else c += (y - t) + s;
+        s = t;
+    }
+    return s + c;
+}
+
+/* ------------------------------------------------------------------------
+ * THRESHOLD-CLASSIFY (Algorithm 3, reading R6).
+ *   Apply-Threshold: A = A_rel AND (E > t)  (threshold-finished regions join
+ *   the rel-err-finished ones);
+ *   memory requirement: more than half of the s_it regions finished;
+ *   accuracy requirement: finished error <= P_max * (e_it - e_b) with
+ *   e_b = e_tot - tau |v_tot| the excess error that the active regions
+ *   still have to shed; e_it - e_b = tau |v_tot| - e_f is the error that
+ *   finished regions may carry without making convergence impossible
+ *   (Section 3.5.3 states that finishing more than that rules out
+ *   convergence, which the literal comparison with e_b does not prevent);
+ *   memory fails  -> raise t halfway to max(E);
+ *   accuracy fails-> lower t halfway to min(E);
+ *   when the search runs because the list would overflow its memory cap
+ *   (memory_pressure), each change of direction adds 0.10 to P_max (at
+ *   most 0.95): Section 3.5.2 presents giving up accuracy budget as the
+ *   price of being able to continue at all, which only that case pays;
+ *   when it runs because the estimate's digits have settled, P_max stays
+ *   at 0.25. The search gives up after 10 direction changes or 64 trials
+ *   and then leaves A_rel unchanged.
+ * Returns 1 on success (Aout and *t_out set), 0 on failure (Aout = A_rel).
+ * ---------------------------------------------------------------------- */
+#define OR_THR_MAX_TRIALS 64
+#define OR_THR_MAX_DIRCHG 10
+
+int oracle_threshold_search(long s_it, const double *E, const uint8_t *A_rel,
+                            double v_tot, double e_tot, double e_it,
+                            double tau_rel, int memory_pressure,
+                            uint8_t *Aout, double *t_out,
+                            int *trials_out, double *tried /* [64] or NULL */)
+{
+    double P_max = 0.25, mn, mx, e_b, t, e_abar;
+    long i, s_abar, n_act;
+    int trials = 0, dir = 0, last_dir = 0, dir_changes = 0;
+
+    mn = INFINITY; mx = -INFINITY;
+    for (i = 0; i < s_it; i++) {
+        if (E[i] < mn) mn = E[i];
+        if (E[i] > mx) mx = E[i];
+    }
+    e_b = e_tot - tau_rel * fabs(v_tot);
+    t = e_it / (double)s_it;
+
+    while (trials < OR_THR_MAX_TRIALS) {
+        if (tried) tried[trials] = t;
+        trials++;
+        n_act = 0;
+        for (i = 0; i < s_it; i++) {
+            Aout[i] = (uint8_t)(A_rel[i] && E[i] > t);
+            n_act += Aout[i];
+        }
+        s_abar = s_it - n_act;
+        e_abar = e_it - oracle_sum(s_it, E, Aout);
+        if ((double)s_abar > 0.5 * (double)s_it) {
+            if (e_abar <= P_max * (e_it - e_b)) {
+                *t_out = t;
+                *trials_out = trials;
+                return 1;
+            }
+            dir = -1;                         /* accuracy failed: lower t */
+        } else {
+            dir = +1;                         /* memory failed: raise t */
+        }
+        if (last_dir != 0 && dir != last_dir) {
+            dir_changes++;
+            if (memory_pressure) {
+                P_max = P_max + 0.10;
+                if (P_max > 0.95) P_max = 0.95;
+            }
+            if (dir_changes >= OR_THR_MAX_DIRCHG) break;
+        }
+        last_dir = dir;
+        if (dir > 0) t = t + (mx - t) / 2.0;
+        else t = t - (t - mn) / 2.0;
+    }
+    memcpy(Aout, A_rel, (size_t)s_it);
+    *t_out = NAN;
+    *trials_out = trials;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * FILTER + parent update + SPLIT (reading R7). Input SoA with leading
+ * dimension ld_in, output SoA with leading dimension ld_out (>= 2 n_a).
+ * Returns n_a, the number of active regions.
+ * ---------------------------------------------------------------------- */
+long oracle_filter_split(int d, long n, const double *lo, const double *w,
+                         long ld_in, const uint8_t *K, const double *V,
+                         const uint8_t *A, double *lo2, double *w2,
+                         long ld_out, double *Vp)
+{
+    long i, j, na = 0;
+    int k;
+    for (i = 0; i < n; i++) na += A[i] ? 1 : 0;
+    j = 0;
+    for (i = 0; i < n; i++) {
+        if (!A[i]) continue;
+        for (k = 0; k < d; k++) {
+            double l = lo[k * ld_in + i], ww = w[k * ld_in + i];
+            if (k == K[i]) {
+                double half = ww * 0.5;
+                lo2[k * ld_out + j] = l;
+                w2[k * ld_out + j] = half;
+                lo2[k * ld_out + j + na] = l + half;
+                w2[k * ld_out + j + na] = half;
+            } else {
+                lo2[k * ld_out + j] = l;
+                w2[k * ld_out + j] = ww;
+                lo2[k * ld_out + j + na] = l;
+                w2[k * ld_out + j + na] = ww;
+            }
+        }
+        Vp[j] = V[i];
+        j++;
+    }
+    return na;
+}
+
+/* UNIFORM-SPLIT (Section 3.1): g^d equal boxes, axis 0 varying fastest. */
+long oracle_uniform_split(int d, const double *a, const double *b, int g,
+                          double *lo, double *w, long ld)
+{
+    long n = 1, r;
+    int k;
+    for (k = 0; k < d; k++) n *= g;
+    for (r = 0; r < n; r++) {
+        long q = r;
+        for (k = 0; k < d; k++) {
+            long digit = q % g;
+            double width = (b[k] - a[k]) / (double)g;
+            q /= g;
+            lo[k * ld + r] = a[k] + (double)digit * width;
+            w[k * ld + r] = width;
+        }
+    }
+    return n;
+}
+
+/* ------------------------------------------------------------------------
+ * Replay trace (file format written by the GPU library on request):
+ *   header : char magic[8] = "PGTRACE1"; int32 d; int32 family;
+ *            int64 reserved[2]
+ *   record : int64 it, n, n_active;
+ *            int32 thr_invoked, thr_ok, thr_trials, terminal;
+ *            double t, v, e, v_f, e_f;
+ *            uint8 K[n]; uint8 A[n]          (A = final active flags)
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int64_t it, n, n_active;
+    int32_t thr_invoked, thr_ok, thr_trials, terminal;
+    double t, v, e, v_f, e_f;
+} or_rec;
+
+/* Counters reported by a replayed run. */
+typedef struct {
+    int64_t axis_override, axis_hard;
+    int64_t class_override, class_hard;
+    int64_t term_override, term_hard;
+    int64_t trig_override, trig_hard;
+    int64_t search_hard;            /* search outcome / trial count / t differs */
+    int64_t thr_override, thr_hard;
+    int64_t records;
+    double max_t_rel;               /* max |t_gpu - t_cpu| / t_cpu */
+    double max_v_rel, max_e_rel;    /* per-iteration v, e sums */
+} or_replay_stats;
+
+/* ------------------------------------------------------------------------
+ * PAGANI main loop (Algorithm 2). Result layout:
+ *   out_d[0] estimate, [1] error, [2] evaluate seconds, [3] total seconds
+ *   out_i[0] status, [1] iterations, [2] regions evaluated, [3] f evals,
+ *        [4] peak regions, [5] threshold invocations, [6] threshold trials
+ * When replay_path is set the run follows the decisions recorded in that
+ * trace and fills *rs; otherwise rs may be NULL.
+ * ---------------------------------------------------------------------- */
+static double now_s(void)
+{
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+int oracle_integrate(int family, int d, const double *par,
+                     const double *a, const double *b,
+                     double tau_rel, double tau_abs, int g, int it_max,
+                     int relerr_filter, int threshold_filter,
+                     int64_t max_regions, const char *replay_path,
+                     double *out_d, int64_t *out_i, or_replay_stats *rs)
+{
+    double w7[5], w5[5], lam[5];
+    double *lo = NULL, *w = NULL, *lo2 = NULL, *w2 = NULL;
+    double *V = NULL, *E = NULL, *Vp = NULL, *Dd = NULL, *fV = NULL, *fE = NULL;
+    double *fD = NULL;
+    uint8_t *K = NULL, *A = NULL, *A_rel = NULL, *Kg = NULL, *Ag = NULL;
+    double v, e, v_f = 0.0, e_f = 0.0, v_tot = 0.0, e_tot = 0.0;
+    double prev_vtot = NAN, t_eval = 0.0, t0;
+    int64_t s, cap, it, status = OR_MAX_ITERS, n_eval = 0, peak = 0;
+    int64_t thr_calls = 0, thr_trials = 0;
+    long i;
+    int k, rc = OR_OK, verbose;
+    FILE *tr = NULL;
+    or_rec rec;
+
+    if (d < 1 || d > OR_DMAX || g < 1 || it_max < 1) return OR_EINVAL;
+    if (!(tau_rel > 0.0) && !(tau_abs > 0.0)) return OR_EINVAL;
+    for (k = 0; k < d; k++) if (!(a[k] < b[k])) return OR_EINVAL;
+    s = 1;
+    for (k = 0; k < d; k++) s *= g;
+    cap = max_regions > 0 ? max_regions : (int64_t)1 << 22;
+    if (s > cap) return OR_EINVAL;
+
+    if (replay_path) {
+        char magic[8];
+        int32_t hd[2];
+        int64_t res[2];
+        tr = fopen(replay_path, "rb");
+        if (!tr) return OR_EREPLAY;
+        if (fread(magic, 1, 8, tr) != 8 || memcmp(magic, "PGTRACE1", 8) ||
+            fread(hd, 4, 2, tr) != 2 || fread(res, 8, 2, tr) != 2 ||
+            hd[0] != d || hd[1] != family) {
+            fclose(tr);
+            return OR_EREPLAY;
+        }
+        if (rs) memset(rs, 0, sizeof(*rs));
+    }
+
+    lo = malloc(sizeof(double) * d * cap);
+    w = malloc(sizeof(double) * d * cap);
+    lo2 = malloc(sizeof(double) * d * cap);
+    w2 = malloc(sizeof(double) * d * cap);
+    V = malloc(sizeof(double) * cap);
+    E = malloc(sizeof(double) * cap);
+    Vp = malloc(sizeof(double) * cap);
+    Dd = malloc(sizeof(double) * d * cap);
+    fV = malloc(sizeof(double) * cap);
+    fE = malloc(sizeof(double) * cap);
+    fD = malloc(sizeof(double) * cap);
+    K = malloc(cap);
+    A = malloc(cap);
+    A_rel = malloc(cap);
+    Kg = malloc(cap);
+    Ag = malloc(cap);
+    if (!lo || !w || !lo2 || !w2 || !V || !E || !Vp || !Dd || !fV || !fE || !fD ||
+        !K || !A || !A_rel || !Kg || !Ag) {
+        rc = OR_ENOMEM;
+        goto done;
+    }
+    oracle_rule(d, w7, w5, lam);
+    verbose = getenv("PAGANI_ORACLE_VERBOSE") != NULL;
+    t0 = now_s();
+
+    /* set-up of Algorithm 2: R0 = b, s = g^d, H = Uniform-Split(R0, g) */
+    oracle_uniform_split(d, a, b, g, lo, w, s);
+    peak = s;
+
+    for (it = 1; it <= it_max; it++) {
+        int64_t n_rel, n_act;
+        int terminated, trig_a, trig_b, invoke, ok = 0, trials = 0;
+        double t = NAN, t1;
+
+        if (tr) {
+            if (fread(&rec, sizeof(rec), 1, tr) != 1 || rec.it != it ||
+                rec.n != s || fread(Kg, 1, s, tr) != (size_t)s ||
+                fread(Ag, 1, s, tr) != (size_t)s) {
+                rc = OR_EREPLAY;
+                goto done;
+            }
+            if (rs) rs->records++;
+        }
+
+        /* Evaluate: V, E, K for every region of H */
+        t1 = now_s();
+        oracle_eval_regions(family, d, par, s, lo, w, s, V, E, K, Dd, fV, fE, fD);
+        t_eval += now_s() - t1;
+        n_eval += s;
+
+        if (tr) {              /* follow the GPU's axis where it is a tie */
+            for (i = 0; i < s; i++) {
+                double *D = Dd + i * d, dmax = 0.0, slack, edge;
+                int kg = Kg[i], cert = 1, j;
+                if (K[i] == Kg[i]) continue;
+                for (j = 0; j < d; j++) if (D[j] > dmax) dmax = D[j];
+                /* an axis is ambiguous when it lies within the rounding
+                   slack of the tie band's lower edge */
+                slack = 1e-12 * dmax + fD[i];
+                edge = dmax * (1.0 - OR_AXIS_TIE) - fD[i];
+                if (kg >= d || D[kg] < edge - slack) cert = 0;
+                for (j = 0; j < d && cert; j++) {
+                    if (j == kg || D[j] < edge + slack) continue;
+                    /* j is surely tied: it must not beat kg in tie order */
+                    if (w[j * s + i] > w[kg * s + i] ||
+                        (w[j * s + i] == w[kg * s + i] && j < kg))
+                        cert = 0;
+                }
+                if (rs) {
+                    if (cert) rs->axis_override++;
+                    else rs->axis_hard++;
+                }
+                K[i] = Kg[i];
+            }
+        }
+
+        /* Two-Level-Error: needs the parents, so not on the first pass */
+        if (it > 1)
+            oracle_two_level(s / 2, V, E, Vp);
+
+        /* Rel-Err-Classify */
+        oracle_classify(s, V, E, tau_rel, relerr_filter, A_rel);
+
+        /* Sum(V), Sum(E) */
+        v = oracle_sum(s, V, NULL);
+        e = oracle_sum(s, E, NULL);
+        v_tot = v + v_f;
+        e_tot = e + e_f;
+
+        /* termination test, with the finished contributions added */
+        terminated = (e_tot <= tau_rel * fabs(v_tot)) || (e_tot <= tau_abs);
+        if (tr) {
+            if (rs) {
+                double rv = fabs(rec.v - v) / (fabs(v) > 0 ? fabs(v) : 1.0);
+                double re = fabs(rec.e - e) / (fabs(e) > 0 ? fabs(e) : 1.0);
+                if (rv > rs->max_v_rel) rs->max_v_rel = rv;
+                if (re > rs->max_e_rel) rs->max_e_rel = re;
+            }
+            if ((rec.terminal == OR_OK) != terminated) {
+                double gap = fabs(e_tot - tau_rel * fabs(v_tot));
+                int cert = gap <= 1e-9 * e_tot;
+                if (rs) { if (cert) rs->term_override++; else rs->term_hard++; }
+                terminated = rec.terminal == OR_OK;
+            }
+        }
+        if (terminated) {
+            status = OR_OK;
+            break;
+        }
+
+        n_rel = 0;
+        for (i = 0; i < s; i++) n_rel += A_rel[i];
+        memcpy(A, A_rel, s);
+
+        /* Threshold-Classify, invoked only in the two cases of Section 3.5.2 */
+        trig_a = threshold_filter && it >= 2 &&
+                 fabs(v_tot - prev_vtot) <= tau_rel * fabs(v_tot);
+        trig_b = threshold_filter && 2 * n_rel > cap;
+        invoke = trig_a || trig_b;
+        if (tr && invoke != (rec.thr_invoked != 0)) {
+            double gap = fabs(fabs(v_tot - prev_vtot) - tau_rel * fabs(v_tot));
+            int cert = gap <= 1e-9 * tau_rel * fabs(v_tot) && !trig_b;
+            if (rs) { if (cert) rs->trig_override++; else rs->trig_hard++; }
+            invoke = rec.thr_invoked != 0;
+        }
+        if (invoke) {
+            thr_calls++;
+            ok = oracle_threshold_search(s, E, A_rel, v_tot, e_tot, e, tau_rel,
+                                         2 * n_rel > cap, A, &t, &trials,
+                                         NULL);
+            thr_trials += trials;
+            if (tr) {
+                if (ok != (rec.thr_ok != 0) || trials != rec.thr_trials) {
+                    if (rs) rs->search_hard++;
+                } else if (ok && rs) {
+                    double r = fabs(rec.t - t) / t;
+                    if (r > rs->max_t_rel) rs->max_t_rel = r;
+                    if (r > 1e-9) rs->search_hard++;
+                }
+                ok = rec.thr_ok != 0;
+                if (ok && !(t == t)) t = rec.t;
+            }
+            if (!ok && 2 * n_rel > cap) {
+                status = OR_MEMORY_EXHAUSTED;
+                break;
+            }
+            if (!ok) memcpy(A, A_rel, s);
+        } else if (2 * n_rel > cap) {
+            status = OR_MEMORY_EXHAUSTED;
+            break;
+        }
+
+        if (tr) {              /* follow the GPU's classification at ties */
+            double tg = rec.t == rec.t ? rec.t : t;
+            for (i = 0; i < s; i++) {
+                int c_rel, c_thr;
+                if (A[i] == Ag[i]) continue;
+                /* E carries the raw-error floor plus, after the two-level
+                   step, the rounding of delta (a few ulps of |V|) */
+                c_rel = fabs(E[i] - tau_rel * fabs(V[i])) <=
+                        1e-12 * E[i] + fE[i] + fV[i] + tau_rel * fV[i];
+                c_thr = ok && fabs(E[i] - t) <= 1e-12 * t + fabs(tg - t) + fE[i];
+                if (rs) {
+                    if (c_rel) rs->class_override++;
+                    else if (c_thr) rs->thr_override++;
+                    else if (ok && A_rel[i] && Ag[i] == 0) rs->thr_hard++;
+                    else rs->class_hard++;
+                }
+                A[i] = Ag[i];
+            }
+        }
+        prev_vtot = v_tot;
+
+        n_act = 0;
+        for (i = 0; i < s; i++) n_act += A[i];
+        if (verbose)
+            fprintf(stderr, "it %2ld n %9ld rel-active %9ld active %9ld "
+                    "v %.12e e %.3e v_f %.6e e_f %.3e thr %d ok %d t %.3e "
+                    "trials %d\n", (long)it, (long)s, (long)n_rel,
+                    (long)n_act, v, e, v_f, e_f, invoke, ok, t, trials);
+        if (n_act == 0) {
+            status = OR_NO_ACTIVE;
+            break;
+        }
+        if (it == it_max) {
+            status = OR_MAX_ITERS;
+            break;
+        }
+
+        /* finished contributions v_f, e_f */
+        v_f = v - oracle_sum(s, V, A) + v_f;
+        e_f = e - oracle_sum(s, E, A) + e_f;
+
+        /* Filter, parent update V_p <- V, Split */
+        oracle_filter_split(d, s, lo, w, s, K, V, A, lo2, w2, 2 * n_act, Vp);
+        {
+            double *tmp;
+            tmp = lo; lo = lo2; lo2 = tmp;
+            tmp = w; w = w2; w2 = tmp;
+        }
+        /* the new list holds the two children of every survivor */
+        s = 2 * n_act;
+        if (s > peak) peak = s;
+    }
+    if (it > it_max) it = it_max;
+
+    out_d[0] = v_tot;
+    out_d[1] = e_tot;
+    out_d[2] = t_eval;
+    out_d[3] = now_s() - t0;
+    out_i[0] = status;
+    out_i[1] = it;
+    out_i[2] = n_eval;
+    out_i[3] = n_eval * oracle_npoints(d);
+    out_i[4] = peak;
+    out_i[5] = thr_calls;
+    out_i[6] = thr_trials;
+
+done:
+    if (tr) fclose(tr);
+    free(lo); free(w); free(lo2); free(w2); free(V); free(E); free(Vp);
+    free(Dd); free(fV); free(fE); free(fD); free(K); free(A); free(A_rel); free(Kg);
+    free(Ag);
+    return rc;
+}

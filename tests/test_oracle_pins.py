@@ -1,0 +1,448 @@
+"""Pins for the CPU oracle: checks against what the mathematics fixes.
+
+Every check here is independent of the oracle's own formulas: exact rational
+integrals of monomials, closed-form integrals of the workloads, invariants
+of the algorithm's steps (Lemma 1, volume conservation, the requirements of
+the threshold search) and brute force on tiny inputs.
+"""
+from fractions import Fraction
+from itertools import combinations_with_replacement, product
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from workloads import closed_forms as cf
+
+EPS = np.finfo(np.float64).eps
+
+
+def _monomials(d, deg):
+    """All exponent vectors of total degree exactly ``deg`` in d variables."""
+    out = []
+    for combo in combinations_with_replacement(range(d), deg):
+        a = [0] * d
+        for i in combo:
+            a[i] += 1
+        out.append(a)
+    return out
+
+
+def _dyadic_boxes(d, n, seed):
+    rng = np.random.default_rng(seed)
+    lo = rng.integers(-8, 8, size=(d, n)) / 8.0          # multiples of 1/8
+    w = rng.integers(1, 9, size=(d, n)) / 8.0
+    return lo, w
+
+
+# ---------------------------------------------------------------------------
+# Cubature rule (Sections 2.1 and 3.2: the Genz-Malik degree-7 rule)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d,n", [(2, 17), (3, 33), (4, 57), (5, 93), (6, 149),
+                                 (7, 241), (8, 401), (10, 1245)])
+def test_point_count(d, n):
+    # 2^d + Theta(d^3) points in the paper's count; the rule has 2^d+2d^2+2d+1
+    assert oracle.npoints(d) == n == 2 ** d + 2 * d * d + 2 * d + 1
+
+
+@pytest.mark.parametrize("d", range(2, 11))
+def test_weights_integrate_constants(d):
+    """The rule and its embedded rule integrate f = 1 to the box volume."""
+    lo, w = _dyadic_boxes(d, 5, seed=d)
+    r = oracle.eval_regions("monomial", d, np.zeros(d), lo, w)
+    vol = np.prod(w, axis=0)
+    np.testing.assert_allclose(r.V, vol, rtol=1e-14)
+    assert np.all(r.E <= 1e-14 * vol)
+
+
+@pytest.mark.parametrize("d", [2, 3, 4, 5, 6, 8])
+def test_degree7_exact_on_every_monomial(d):
+    """R7 is exact for every monomial of total degree <= 7 on any box."""
+    lo, w = _dyadic_boxes(d, 2, seed=100 + d)
+    degs = range(0, 8) if d <= 5 else [0, 1, 2, 3, 6, 7]
+    worst = 0.0
+    for deg in degs:
+        for alpha in _monomials(d, deg):
+            r = oracle.eval_regions("monomial", d, np.array(alpha, float), lo, w)
+            for j in range(lo.shape[1]):
+                exact = cf.monomial(alpha, lo[:, j], lo[:, j] + w[:, j])
+                err = abs(Fraction(r.V[j]) - exact)
+                bound = Fraction(r.floorV[j]) + Fraction(1e-300)
+                assert err <= bound, (alpha, j, float(err), float(bound))
+                if exact != 0:
+                    worst = max(worst, float(err / abs(exact)))
+    assert worst < 1e-12
+
+
+@pytest.mark.parametrize("d", [2, 3, 5, 8])
+def test_degree8_not_exact(d):
+    """...but not for degree 8: x_1^8 on [-1,1]^d is integrated wrongly,
+    which pins the degree (a rule of higher degree would be exact)."""
+    lo, w = -np.ones((d, 1)), 2 * np.ones((d, 1))
+    alpha = [8] + [0] * (d - 1)
+    r = oracle.eval_regions("monomial", d, np.array(alpha, float), lo, w)
+    exact = float(cf.monomial(alpha, lo[:, 0], lo[:, 0] + w[:, 0]))
+    assert abs(r.V[0] - exact) > 1e-3 * exact
+
+
+@pytest.mark.parametrize("d", [2, 3, 4, 5, 6])
+def test_null_rule_vanishes_to_degree5(d):
+    """E = |R7 - R5| is zero (to rounding) on every monomial of degree <= 5,
+    because both rules are exact there."""
+    lo, w = _dyadic_boxes(d, 2, seed=200 + d)
+    for deg in range(0, 6):
+        for alpha in _monomials(d, deg):
+            r = oracle.eval_regions("monomial", d, np.array(alpha, float), lo, w)
+            assert np.all(r.E <= r.floorE), (alpha, r.E, r.floorE)
+
+
+@pytest.mark.parametrize("d", [2, 3, 5, 6, 8, 10])
+def test_null_rule_value_on_x6(d):
+    """On [-1,1]^d, R7(x_i^6) = 2^d / 7 (exact) and R5(x_i^6) = 2^d 117/700,
+    so E / vol = 17/700 independently of d and of the axis."""
+    lo, w = -np.ones((d, 1)), 2 * np.ones((d, 1))
+    for i in range(d):
+        alpha = [0] * d
+        alpha[i] = 6
+        r = oracle.eval_regions("monomial", d, np.array(alpha, float), lo, w)
+        assert r.E[0] / 2 ** d == pytest.approx(17 / 700, rel=1e-13)
+        assert r.V[0] / 2 ** d == pytest.approx(1 / 7, rel=1e-13)
+
+
+@pytest.mark.parametrize("d", [2, 3, 5, 8])
+def test_rule_is_fully_symmetric(d):
+    """Permuting the axes of the integrand and of the box permutes nothing in
+    V and E (the point set is invariant under axis permutations and
+    reflections)."""
+    rng = np.random.default_rng(d)
+    lo, w = _dyadic_boxes(d, 3, seed=300 + d)
+    p = W.gaussian_params(d, seed=7)
+    perm = rng.permutation(d)
+    r1 = oracle.eval_regions("gaussian", d, p, lo, w)
+    p2 = np.concatenate([p[:d][perm], p[d:][perm]])
+    r2 = oracle.eval_regions("gaussian", d, p2, lo[perm], w[perm])
+    np.testing.assert_allclose(r1.V, r2.V, rtol=1e-13)
+    np.testing.assert_allclose(r1.E, r2.E, rtol=1e-9, atol=1e-14 * np.abs(r1.V).max())
+
+
+# ---------------------------------------------------------------------------
+# Split axis: fourth divided differences (reading of the split rule)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d", [2, 3, 5, 8])
+def test_fourth_difference_of_x4(d):
+    """For f = x_k^4 on [-1,1]^d: D_k = 2 l2^4 - (2/7) l3^4 = 243/1225, every
+    other D_j = 0, so the split axis is k."""
+    lo, w = -np.ones((d, 1)), 2 * np.ones((d, 1))
+    for k in range(d):
+        alpha = [0] * d
+        alpha[k] = 4
+        r = oracle.eval_regions("monomial", d, np.array(alpha, float), lo, w)
+        assert r.K[0] == k
+        assert r.D[0, k] == pytest.approx(243 / 1225, rel=1e-14)
+        others = np.delete(r.D[0], k)
+        assert np.all(others <= 1e-15)
+
+
+@pytest.mark.parametrize("d", [3, 5])
+def test_fourth_difference_blind_to_cubics(d):
+    """D_i = 0 for any polynomial of degree <= 3 in x_i; with every D zero
+    the widest axis is split (lowest index among equal widths)."""
+    w = np.ones((d, 1))
+    w[2, 0] = 2.0
+    lo = np.zeros((d, 1))
+    for alpha in _monomials(d, 3) + _monomials(d, 2):
+        r = oracle.eval_regions("monomial", d, np.array(alpha, float), lo, w)
+        assert np.all(r.D[0] <= r.floorD[0] + 1e-15)
+        assert r.K[0] == 2
+    r = oracle.eval_regions("monomial", d, np.zeros(d), np.zeros((d, 1)),
+                            np.ones((d, 1)))
+    assert r.K[0] == 0
+
+
+def test_split_axis_follows_the_steep_direction():
+    """A Gaussian ridge steep along axis 1 only is split along axis 1."""
+    d = 3
+    p = np.array([1.0, 40.0, 1.0, 0.5, 0.37, 0.5])
+    lo, w = np.zeros((d, 1)), np.ones((d, 1))
+    r = oracle.eval_regions("gaussian", d, p, lo, w)
+    assert r.K[0] == 1
+
+
+# ---------------------------------------------------------------------------
+# Uniform-Split, two-level error, classification, sums
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d,g", [(2, 3), (3, 4), (5, 4), (8, 2)])
+def test_uniform_split_tiles_the_domain(d, g):
+    a = np.linspace(-1.0, 0.0, d)
+    b = a + np.linspace(1.0, 2.0, d)
+    lo, w = oracle.uniform_split(d, a, b, g)
+    assert lo.shape == (d, g ** d)
+    # axis 0 varies fastest
+    np.testing.assert_allclose(lo[0, :g], a[0] + np.arange(g) * (b[0] - a[0]) / g)
+    assert np.all(lo[1:, :g] == lo[1:, :1])
+    # cells are distinct and tile the box
+    cells = {tuple(np.round((lo[:, j] - a) / w[:, j]).astype(int)) for j in range(g ** d)}
+    assert len(cells) == g ** d
+    assert np.prod(w, axis=0).sum() == pytest.approx(np.prod(b - a), rel=1e-13)
+
+
+def test_two_level_properties():
+    rng = np.random.default_rng(11)
+    m = 200
+    V = rng.normal(size=2 * m)
+    E = rng.uniform(0, 1e-3, size=2 * m)
+    E[:5] = 0.0
+    E[m:m + 5] = 0.0
+    Vp = V[:m] + V[m:] + rng.normal(scale=1e-3, size=m)
+    Vp[10:20] = V[10:20] + V[m + 10:m + 20]          # children agree with parent
+    E2 = oracle.two_level(V, E, Vp)
+    delta = np.abs(V[:m] + V[m:] - Vp) / 4
+    # pair totals grow by exactly 4 delta (up to rounding) when S > 0
+    S = E[:m] + E[m:]
+    pos = S > 0
+    np.testing.assert_allclose((E2[:m] + E2[m:])[pos], (S + 4 * delta)[pos],
+                               rtol=1e-13, atol=1e-300)
+    # refinement never lowers an error; agreement leaves it untouched
+    assert np.all(E2 >= E)
+    np.testing.assert_array_equal(E2[10:20], E[10:20])
+    # S = 0: each sibling gets delta
+    np.testing.assert_allclose(E2[:5], delta[:5], rtol=1e-15)
+    # hand-worked pair: Va=1, Vb=2, Vp=3.4, Ea=0.1, Eb=0.3
+    #   delta = 0.1, S = 0.4, factor = 1 + 2*0.1/0.4 = 1.5
+    #   Ea' = 0.15 + 0.1 = 0.25, Eb' = 0.45 + 0.1 = 0.55
+    e = oracle.two_level([1.0, 2.0], [0.1, 0.3], [3.4])
+    np.testing.assert_allclose(e, [0.25, 0.55], rtol=1e-14)
+
+
+def test_classify_semantics():
+    V = np.array([1.0, -2.0, 0.0, 1.0, 5.0])
+    E = np.array([1e-4, 2e-4, 0.0, 1.1e-4, 1.0])
+    A = oracle.classify(V, E, 1e-4)
+    # E <= tau |V| finishes (equality included, zero regions finish)
+    np.testing.assert_array_equal(A, [0, 0, 0, 1, 1])
+    np.testing.assert_array_equal(oracle.classify(V, E, 1e-4, 0), [1] * 5)
+
+
+@pytest.mark.parametrize("sign", [1.0, -1.0])
+def test_lemma1(sign):
+    """Lemma 1 (Section 3.5.1): same-sign V_i with E_i <= tau |V_i| give
+    e <= tau |v|; regions the classifier finishes satisfy the premise."""
+    rng = np.random.default_rng(3)
+    tau = 1e-5
+    V = sign * rng.lognormal(size=10000)
+    E = tau * np.abs(V) * rng.uniform(0, 2, size=V.size)
+    A = oracle.classify(V, E, tau)
+    fin = A == 0
+    assert fin.any() and (~fin).any()
+    e = oracle.csum(E[fin])
+    v = oracle.csum(V[fin])
+    assert e <= tau * abs(v)
+
+
+def test_compensated_sum():
+    rng = np.random.default_rng(5)
+    x = rng.normal(size=100000) * 10.0 ** rng.integers(-10, 10, size=100000)
+    assert oracle.csum(x) == pytest.approx(math.fsum(x), rel=1e-15, abs=1e-300)
+    m = (rng.uniform(size=x.size) < 0.3).astype(np.uint8)
+    assert oracle.csum(x, m) == pytest.approx(math.fsum(x[m == 1]), rel=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Threshold-Classify (Algorithm 3)
+# ---------------------------------------------------------------------------
+
+def _check_search_result(E, A_rel, v_tot, e_tot, e_it, tau, mem, res):
+    ok, A, t, trials, tried = res
+    s = len(E)
+    assert 1 <= trials <= 64
+    if not ok:
+        np.testing.assert_array_equal(A, A_rel)
+        return
+    np.testing.assert_array_equal(A, (A_rel.astype(bool) & (E > t)).astype(np.uint8))
+    fin = A == 0
+    e_b = e_tot - tau * abs(v_tot)
+    # memory requirement: more than half finished
+    assert fin.sum() > 0.5 * s
+    # accuracy requirement with the largest P_max the search may reach
+    p_cap = 0.95 if mem else 0.25
+    assert math.fsum(E[fin]) <= p_cap * (e_it - e_b) * (1 + 1e-12)
+    # the accepted threshold was the last one tried
+    assert tried[-1] == t
+    # thresholds stay inside [min E, max E]
+    assert np.all(tried >= E.min()) and np.all(tried <= E.max())
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_threshold_search_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    s = int(rng.integers(4, 40))
+    E = rng.lognormal(sigma=3.0, size=s) * 1e-6
+    A_rel = (rng.uniform(size=s) < 0.85).astype(np.uint8)
+    V = rng.uniform(0.5, 1.5, size=s)
+    v = V.sum()
+    e_it = math.fsum(E)
+    tau = float(10.0 ** rng.uniform(-5, -2))
+    e_f = float(rng.uniform(0, 0.5)) * tau * v
+    e_tot = e_it + e_f
+    mem = bool(rng.integers(0, 2))
+    res = oracle.threshold_search(E, A_rel, v, e_tot, e_it, tau, mem)
+    _check_search_result(E, A_rel, v, e_tot, e_it, tau, mem, res)
+    # brute force: if some candidate threshold satisfies both requirements at
+    # P_max = 0.25 and the first trial (the mean) is feasible, it is accepted
+    t0 = e_it / s
+    A0 = A_rel.astype(bool) & (E > t0)
+    e_b = e_tot - tau * v
+    first_ok = ((~A0).sum() > 0.5 * s and
+                math.fsum(E[~A0]) <= 0.25 * (e_it - e_b))
+    if first_ok:
+        assert res[0] and res[3] == 1 and res[2] == t0
+
+
+def test_threshold_search_worked_example():
+    """Eight regions; hand-traced trajectory.
+
+    E = [1,2,...,8] * 1e-3, all rel-err active, tau = 1e-3, v_tot = 20,
+    e_f = 0 so e_it = e_tot = 0.036 and the allowance e_it - e_b = 0.02.
+      trial 1: t = mean = 4.5e-3 -> finished {1..4} -> 4 of 8, memory fails
+               -> raise: t = 4.5e-3 + (8e-3 - 4.5e-3)/2 = 6.25e-3
+      trial 2: finished {1..6}: 6 > 4, error 0.021 > 0.25*0.02 -> lower:
+               t = 6.25e-3 - (6.25e-3 - 1e-3)/2 = 3.625e-3 (direction change 1)
+      trial 3: finished {1..3}: memory fails -> raise: t = 5.8125e-3 (2)
+      ... the search alternates without a feasible threshold (5 of the 8
+      regions carry 0.015 > 0.005) and fails after 10 direction changes.
+    """
+    E = np.arange(1, 9) * 1e-3
+    A_rel = np.ones(8, np.uint8)
+    ok, A, t, trials, tried = oracle.threshold_search(E, A_rel, 20.0, 0.036,
+                                                      0.036, 1e-3, False)
+    assert not ok
+    np.testing.assert_array_equal(A, A_rel)
+    np.testing.assert_allclose(tried[:3], [4.5e-3, 6.25e-3, 3.625e-3], rtol=1e-15)
+    assert tried[3] == pytest.approx(3.625e-3 + (8e-3 - 3.625e-3) / 2, rel=1e-15)
+    assert trials == 11
+    # with memory pressure P_max grows to 0.95 * 0.02 = 0.019, but 5 regions
+    # still carry 0.015 only if the threshold lands between 5e-3 and 6e-3
+    ok, A, t, trials, tried = oracle.threshold_search(E, A_rel, 20.0, 0.036,
+                                                      0.036, 1e-3, True)
+    assert ok
+    assert 5e-3 <= t < 6e-3
+    np.testing.assert_array_equal(A, [0, 0, 0, 0, 0, 1, 1, 1])
+
+
+# ---------------------------------------------------------------------------
+# Filter + Split
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d", [2, 5, 8])
+def test_filter_split_against_mask(d):
+    rng = np.random.default_rng(d)
+    n = 301
+    lo, w = W.random_boxes(d, n, seed=d, dyadic_bits=10)
+    K = rng.integers(0, d, size=n).astype(np.uint8)
+    V = rng.normal(size=n)
+    A = (rng.uniform(size=n) < 0.6).astype(np.uint8)
+    lo2, w2, Vp = oracle.filter_split(d, lo, w, K, V, A)
+    idx = np.flatnonzero(A)
+    na = len(idx)
+    assert lo2.shape == (d, 2 * na)
+    np.testing.assert_array_equal(Vp, V[idx])                   # stable order
+    for half in (0, 1):
+        seg = slice(half * na, (half + 1) * na)
+        for k in range(d):
+            split = K[idx] == k
+            wk = np.where(split, w[k, idx] / 2, w[k, idx])
+            lk = np.where(split & (half == 1), lo[k, idx] + w[k, idx] / 2, lo[k, idx])
+            np.testing.assert_array_equal(w2[k, seg], wk)
+            np.testing.assert_array_equal(lo2[k, seg], lk)
+    # children tile their parent exactly (dyadic boxes: exact arithmetic)
+    vol_par = np.prod(w[:, idx], axis=0)
+    vol_ch = np.prod(w2[:, :na], axis=0) + np.prod(w2[:, na:], axis=0)
+    np.testing.assert_array_equal(vol_ch, vol_par)
+
+
+def test_filter_split_empty():
+    d = 3
+    lo, w = W.random_boxes(d, 10, seed=1)
+    lo2, w2, Vp = oracle.filter_split(d, lo, w, np.zeros(10, np.uint8),
+                                      np.ones(10), np.zeros(10, np.uint8))
+    assert lo2.shape == (d, 0) and len(Vp) == 0
+
+
+# ---------------------------------------------------------------------------
+# Whole runs against the closed forms (Section 4.2's accuracy methodology:
+# compare the true error, not only the estimated one)
+# ---------------------------------------------------------------------------
+
+def _check_run(wl, r):
+    exact = cf.exact(wl.family, wl.params, wl.d)
+    assert r.status_name == "OK", r
+    tau = wl.rel_tol
+    assert abs(r.estimate - exact) <= tau * abs(exact)
+    assert r.error <= tau * abs(r.estimate)
+
+
+def test_free_run_product_peak_d3():
+    wl = W.product_peak_d3()
+    r = oracle.integrate_workload(wl)
+    _check_run(wl, r)
+    assert r.fevals == r.regions_evaluated * 33
+
+
+@pytest.mark.parametrize("tau", [1e-3, 1e-5, 1e-7])
+def test_free_run_product_peak_tolerance_sweep(tau):
+    wl = W.product_peak_d3()
+    wl.rel_tol = tau
+    _check_run(wl, oracle.integrate_workload(wl))
+
+
+def test_free_run_gaussian_d5_reduced():
+    """The d=5 Gaussian at rel_tol 1e-4 (the full 1e-6 run takes ~25 s)."""
+    wl = W.gaussian_d5()
+    wl.rel_tol = 1e-4
+    r = oracle.integrate_workload(wl)
+    _check_run(wl, r)
+    assert r.threshold_calls > 0
+
+
+@pytest.mark.slow
+def test_free_run_gaussian_d5_full():
+    wl = W.gaussian_d5()
+    r = oracle.integrate_workload(wl)
+    _check_run(wl, r)
+    assert r.peak_regions == wl.max_regions          # memory trigger fired
+
+
+def test_free_run_oscillatory_d8():
+    """Sign-changing integrand: with the rel-err filter off the run converges;
+    with it on every region is finished before the total error is small
+    enough (the failure Section 3.5.1 warns about), reported as NO_ACTIVE."""
+    wl = W.oscillatory_d8(relerr_filter=0)
+    _check_run(wl, oracle.integrate_workload(wl))
+    r = oracle.integrate_workload(W.oscillatory_d8(relerr_filter=1))
+    assert r.status_name == "NO_ACTIVE"
+    assert r.error > 1e-5 * abs(r.estimate)
+
+
+def test_free_run_corner_peak_d6():
+    a = W.corner_peak_params(6, seed=9)
+    r = oracle.integrate("corner_peak", 6, a, rel_tol=1e-5, init_splits=2)
+    exact = cf.corner_peak(a, 6)
+    assert r.status_name == "OK"
+    assert abs(r.estimate - exact) <= 1e-5 * abs(exact)
+
+
+def test_status_paths():
+    wl = W.gaussian_d5()
+    r = oracle.integrate_workload(wl, max_iters=1)
+    assert r.status_name == "MAX_ITERS" and r.iterations == 1
+    r = oracle.integrate_workload(wl, max_regions=1500, threshold_filter=0)
+    assert r.status_name == "MEMORY_EXHAUSTED"
+    with pytest.raises(RuntimeError):
+        oracle.integrate_workload(wl, max_regions=100)       # 4^5 > cap
+    with pytest.raises(RuntimeError):
+        oracle.integrate("gaussian", 5, wl.params, rel_tol=0.0, abs_tol=0.0)

@@ -1,0 +1,206 @@
+"""Seeded synthetic workloads for the PAGANI integrator.
+
+This module only draws integrand parameters and tolerances from fixed seeds
+and describes the five benchmark workloads. It contains none of the
+integration method's arithmetic, so that both the GPU library's tests and
+the CPU oracle can take their inputs from it without sharing code.
+
+Parameter draws use ``numpy.random.default_rng(seed)`` and always draw the
+steepness vector ``a`` (all axes) first, then the location vector ``u``.
+
+Integrand families (all on the unit cube unless stated otherwise); the
+paper's own test functions (Section 4.1) belong to the same Genz families:
+
+* ``product_peak``  f(x) = prod_i 1 / (a_i^-2 + (x_i - u_i)^2)
+* ``gaussian``      f(x) = exp(-sum_i a_i^2 (x_i - u_i)^2)
+* ``oscillatory``   f(x) = cos(2 pi u_1 + sum_i a_i x_i)
+* ``corner_peak``   f(x) = (1 + sum_i a_i x_i)^-(d+1)
+* ``monomial``      f(x) = prod_i x_i^alpha_i   (test family, integer alpha)
+
+Parameter vector layout per family (``params``):
+
+* product_peak, gaussian: ``[a_1..a_d, u_1..u_d]``  (2d values)
+* oscillatory:            ``[a_1..a_d, u_1]``        (d+1 values)
+* corner_peak:            ``[a_1..a_d]``             (d values)
+* monomial:               ``[alpha_1..alpha_d]``     (d values, integers)
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import numpy as np
+
+FAMILIES = {
+    "product_peak": 0,
+    "gaussian": 1,
+    "oscillatory": 2,
+    "corner_peak": 3,
+    "monomial": 4,
+}
+
+
+def n_params(family: str, d: int) -> int:
+    """Length of the parameter vector of ``family`` in dimension ``d``."""
+    if family in ("product_peak", "gaussian"):
+        return 2 * d
+    if family == "oscillatory":
+        return d + 1
+    if family in ("corner_peak", "monomial"):
+        return d
+    raise ValueError(f"unknown family {family!r}")
+
+
+@dataclass
+class Workload:
+    """One plain (single-integral) run: integrand, domain and options."""
+    name: str
+    family: str
+    d: int
+    params: np.ndarray
+    rel_tol: float
+    abs_tol: float = 1e-20
+    init_splits: int = 4
+    max_regions: int = 1 << 22
+    max_iters: int = 100
+    relerr_filter: int = 1
+    threshold_filter: int = 1
+    lo: np.ndarray = field(default=None)
+    hi: np.ndarray = field(default=None)
+
+    def __post_init__(self):
+        if self.lo is None:
+            self.lo = np.zeros(self.d)
+        if self.hi is None:
+            self.hi = np.ones(self.d)
+        self.params = np.ascontiguousarray(self.params, dtype=np.float64)
+        self.lo = np.ascontiguousarray(self.lo, dtype=np.float64)
+        self.hi = np.ascontiguousarray(self.hi, dtype=np.float64)
+
+    @property
+    def npoints(self) -> int:
+        """Cubature points per region, 2^d + 2d^2 + 2d + 1."""
+        d = self.d
+        return (1 << d) + 2 * d * d + 2 * d + 1
+
+
+def product_peak_params(d: int, seed: int, a_range=(5.0, 15.0),
+                        u_range=(0.2, 0.8)) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(*a_range, size=d)
+    u = rng.uniform(*u_range, size=d)
+    return np.concatenate([a, u])
+
+
+def gaussian_params(d: int, seed: int, a_range=(10.0, 25.0),
+                    u_range=(0.3, 0.7)) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(*a_range, size=d)
+    u = rng.uniform(*u_range, size=d)
+    return np.concatenate([a, u])
+
+
+def oscillatory_params(d: int, seed: int, a_range=(0.0, 1.5),
+                       a_sum=6.0) -> np.ndarray:
+    """a_i ~ U[a_range] rescaled so that sum_i a_i = a_sum; u_1 ~ U[0, 1]."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(*a_range, size=d)
+    a = a * (a_sum / a.sum())
+    u1 = rng.uniform(0.0, 1.0, size=1)
+    return np.concatenate([a, u1])
+
+
+def corner_peak_params(d: int, seed: int, a_range=(0.0, 2.0)) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return rng.uniform(*a_range, size=d)
+
+
+def monomial_params(alpha) -> np.ndarray:
+    return np.asarray(alpha, dtype=np.float64)
+
+
+# --------------------------------------------------------------------------
+# The five benchmark workloads (sizes and distributions as specified for the
+# MI355X build; the paper's own suite uses the same families, Section 4.1).
+# --------------------------------------------------------------------------
+
+def product_peak_d3() -> Workload:
+    """d=3 product peak, 4^3 initial grid, rel_tol 1e-3 (small case)."""
+    return Workload("product_peak_d3", "product_peak", 3,
+                    product_peak_params(3, seed=1), rel_tol=1e-3,
+                    init_splits=4)
+
+
+def gaussian_d5(max_regions: int = 1 << 21) -> Workload:
+    """d=5 Gaussian, 4^5 initial grid, rel_tol 1e-6 (headline workload).
+
+    The live list is capped at 2^21 regions, below the ~2.6e6 the run would
+    otherwise reach, so that the memory trigger of the threshold search
+    fires during the run."""
+    return Workload("gaussian_d5", "gaussian", 5, gaussian_params(5, seed=2),
+                    rel_tol=1e-6, init_splits=4, max_regions=max_regions)
+
+
+def oscillatory_d8(relerr_filter: int = 1) -> Workload:
+    """d=8 oscillatory (sum a = 6), 2^8 initial grid, rel_tol 1e-5."""
+    return Workload("oscillatory_d8", "oscillatory", 8,
+                    oscillatory_params(8, seed=3), rel_tol=1e-5,
+                    init_splits=2, relerr_filter=relerr_filter)
+
+
+@dataclass
+class BatchWorkload:
+    """Many independent integrals of one family with per-instance params."""
+    name: str
+    family: str
+    d: int
+    params: np.ndarray       # [B, n_params]
+    rel_tol: np.ndarray      # [B]
+    abs_tol: np.ndarray      # [B]
+    init_splits: int = 2
+
+
+def corner_peak_batch_d6(B: int = 1024, seed: int = 4) -> BatchWorkload:
+    """B corner-peak integrals, d=6, a ~ U[0,2] per instance and per-instance
+    rel_tol log-uniform in [1e-7, 1e-4]."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(0.0, 2.0, size=(B, 6))
+    tol = 10.0 ** rng.uniform(-7.0, -4.0, size=B)
+    return BatchWorkload("corner_peak_batch_d6", "corner_peak", 6, a, tol,
+                         np.full(B, 1e-20), init_splits=2)
+
+
+def gaussian_grad_d6(B: int = 256, seed: int = 5) -> BatchWorkload:
+    """B Gaussian parameter points, d=6, theta = (a_1..a_6, u_1..u_6),
+    a ~ U[5,20], u ~ U[0.2,0.8], rel_tol 1e-7."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(5.0, 20.0, size=(B, 6))
+    u = rng.uniform(0.2, 0.8, size=(B, 6))
+    return BatchWorkload("gaussian_grad_d6", "gaussian", 6,
+                         np.concatenate([a, u], axis=1), np.full(B, 1e-7),
+                         np.full(B, 1e-20), init_splits=2)
+
+
+def random_boxes(d: int, n: int, seed: int, lo=0.0, hi=1.0,
+                 dyadic_bits: int = 0):
+    """n random axis-aligned boxes inside [lo, hi]^d, as SoA arrays
+    (lower corners ``[d, n]`` and widths ``[d, n]``).
+
+    With ``dyadic_bits > 0`` every corner and width is a multiple of
+    2^-dyadic_bits, so that box arithmetic (halving, adding half widths) is
+    exact in binary floating point.
+    """
+    rng = np.random.default_rng(seed)
+    if dyadic_bits:
+        m = 1 << dyadic_bits
+        a = rng.integers(0, m, size=(d, n))
+        b = rng.integers(0, m, size=(d, n))
+        l = np.minimum(a, b)
+        wd = np.abs(a - b) + 1
+        wd = np.minimum(wd, m - l)
+        span = hi - lo
+        return lo + span * l / m, span * wd / m
+    x0 = rng.uniform(lo, hi, size=(d, n))
+    x1 = rng.uniform(lo, hi, size=(d, n))
+    l = np.minimum(x0, x1)
+    wd = np.maximum(np.abs(x1 - x0), 1e-3 * (hi - lo))
+    wd = np.minimum(wd, hi - l)
+    return l, wd
