@@ -1,0 +1,223 @@
+/*
+ * pagani.h -- C interface of the MI355X (gfx950) PAGANI integrator.
+ *
+ * PAGANI (Sakiotis et al., SC'21) integrates f over a box by refining every
+ * live sub-region in lock-step (Section 3.1, Algorithm 2): each iteration
+ * evaluates all regions with a degree-7 cubature rule (Section 3.2), refines
+ * the error estimates with the two-level scheme, classifies regions as
+ * finished or active (Section 3.5.1, and Algorithm 3 for the threshold
+ * search of Section 3.5.3), removes the finished ones and bisects the rest.
+ *
+ * Conventions shared by every entry point
+ *  - Return value: a pg_status. Negative values are errors (the message is
+ *    in pg_last_error); PG_OK and the positive values are results.
+ *  - Host pointers are read (or written) only during the call. Device
+ *    pointers must stay valid until the work queued on the context's
+ *    stream has finished; the step entry points only queue work.
+ *  - Region lists are structure-of-arrays in device memory: lower corners
+ *    lo[k * ld + i] and widths w[k * ld + i] for axis k of region i, with
+ *    leading dimension ld >= n. Region i is the box [lo_i, lo_i + w_i].
+ *  - Integrands are a family id plus a parameter vector (no function
+ *    pointers: the integrand is inlined into the evaluation kernel):
+ *      PG_PRODUCT_PEAK  prod_k 1 / (a_k^-2 + (x_k - u_k)^2)  params a[d], u[d]
+ *      PG_GAUSSIAN      exp(-sum_k a_k^2 (x_k - u_k)^2)      params a[d], u[d]
+ *      PG_OSCILLATORY   cos(2 pi u_1 + sum_k a_k x_k)        params a[d], u_1
+ *      PG_CORNER_PEAK   (1 + sum_k a_k x_k)^-(d+1)          params a[d]
+ *      PG_MONOMIAL      prod_k x_k^alpha_k                  params alpha[d]
+ *    (Section 4.1's test functions belong to these families.)
+ *  - Dimensions PG_DIM_MIN..PG_DIM_MAX are supported.
+ *  - One context serves one caller at a time; calls on one context must not
+ *    overlap.
+ */
+#ifndef PAGANI_H
+#define PAGANI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PG_DIM_MIN 2
+#define PG_DIM_MAX 10
+
+typedef enum {
+    PG_OK = 0,                 /* tolerance met */
+    PG_MAX_ITERS = 1,          /* estimate valid, max_iters reached */
+    PG_MEMORY_EXHAUSTED = 2,   /* estimate valid, list would exceed the cap
+                                  and the threshold search failed (Sec. 3.5.2) */
+    PG_NO_ACTIVE = 3,          /* estimate valid, every region finished but
+                                  the tolerance is not met (Sec. 3.5.1) */
+    PG_EINVAL = -1,            /* invalid argument */
+    PG_ENOMEM = -2,            /* workspace too small / allocation failed */
+    PG_EHIP = -3,              /* HIP runtime error */
+    PG_EUNSUPPORTED = -4       /* family or dimension not built */
+} pg_status;
+
+typedef enum {
+    PG_PRODUCT_PEAK = 0,
+    PG_GAUSSIAN = 1,
+    PG_OSCILLATORY = 2,
+    PG_CORNER_PEAK = 3,
+    PG_MONOMIAL = 4
+} pg_family;
+
+typedef struct pg_context pg_context;
+
+typedef struct {
+    int family;               /* pg_family */
+    int dim;                  /* d */
+    const double *params;     /* host array, layout per family (above) */
+    int n_params;             /* 2d, 2d, d+1, d, d */
+} pg_integrand;
+
+typedef struct {
+    double rel_tol;           /* tau_rel (Algorithm 2 input) */
+    double abs_tol;           /* tau_abs */
+    int init_splits;          /* g: the initial grid has g^d equal boxes */
+    int max_iters;            /* it_max */
+    int relerr_filter;        /* 1: classify by relative error (default);
+                                 0: off, for sign-changing integrands (3.5.1) */
+    int threshold_filter;     /* 1: threshold search on (Algorithm 3); 0: off */
+    int64_t max_regions;      /* cap on the live list; 0: context capacity */
+    int timing;               /* 1: time each phase with HIP events */
+    const char *trace_path;   /* non-NULL: write the decision trace (below) */
+} pg_options;
+
+/* Default options: rel_tol 1e-3, abs_tol 1e-20, g = 4, it_max = 100, both
+   filters on, cap = capacity, no timing, no trace. */
+void pg_default_options(pg_options *opt);
+
+typedef struct {
+    double estimate;          /* v + v_f */
+    double error;             /* e + e_f */
+    int status;               /* pg_status (>= 0) */
+    int iterations;
+    int64_t regions_evaluated;/* sum over iterations of the live count */
+    int64_t fevals;           /* regions_evaluated * (2^d + 2d^2 + 2d + 1) */
+    int64_t peak_regions;
+    int64_t threshold_calls;
+    int64_t threshold_trials;
+    double phase_ms[4];       /* with timing: evaluate, post-processing
+                                 (two-level, classify, sums), threshold
+                                 search, filter + split (Section 4.3.2) */
+    int64_t eval_launches;    /* number of evaluate kernel launches */
+} pg_result;
+
+/*
+ * Bytes of device workspace for lists of up to `capacity` regions of up to
+ * `dim_max` dimensions (two ping-pong region lists plus V, E, K, A,
+ * parents and reduction scratch).
+ */
+size_t pg_workspace_bytes(int dim_max, int64_t capacity);
+
+/*
+ * Create a context on HIP device `device`. `workspace` is device memory of
+ * at least pg_workspace_bytes(dim_max, capacity) bytes owned by the caller
+ * (for example a PyTorch tensor's storage), or NULL to let the context
+ * allocate (and later free) it; a caller's workspace must be 256-byte
+ * aligned. `stream` is the hipStream_t all work is queued on, owned by the
+ * caller; NULL is the device's null stream (PyTorch's default stream).
+ * Errors: PG_EINVAL, PG_ENOMEM, PG_EHIP; *out is NULL then.
+ */
+int pg_context_create(int device, int dim_max, int64_t capacity,
+                      void *workspace, size_t ws_bytes, void *stream,
+                      pg_context **out);
+void pg_context_destroy(pg_context *ctx);
+/* Replace the stream work is queued on (a hipStream_t, NULL = null stream). */
+int pg_context_set_stream(pg_context *ctx, void *stream);
+/* Message of the last error on this context ("" if none). */
+const char *pg_last_error(const pg_context *ctx);
+
+/*
+ * Whole run of Algorithm 2 over the box [lo, hi] (host arrays of dim
+ * values). Blocks until the result is known. `out` is always written when
+ * non-NULL; it holds a valid estimate whenever the return value is >= 0.
+ * Errors: PG_EINVAL (lo >= hi on some axis, no positive tolerance, g < 1,
+ * g^d above the cap, bad family/params), PG_ENOMEM (cap above capacity),
+ * PG_EUNSUPPORTED, PG_EHIP.
+ *
+ * Decision trace (when opt->trace_path is set), little endian:
+ *   header  char magic[8] = "PGTRACE1"; int32 d; int32 family; int64 0, 0
+ *   per iteration:
+ *     int64 it, n, n_active; int32 thr_invoked, thr_ok, thr_trials,
+ *     terminal (-1 = continues, else the pg_status the run ends with);
+ *     double t, v, e, v_f, e_f; uint8 K[n]; uint8 A[n] (final flags)
+ */
+int pg_integrate(pg_context *ctx, const pg_integrand *f, const double *lo,
+                 const double *hi, const pg_options *opt, pg_result *out);
+
+/*
+ * View of the live region list as the last pg_integrate left it: the n
+ * regions of its last iteration with their V, (refined) E, split axis K and
+ * rel-err flags A. Device pointers, valid until the next call that uses the
+ * context.
+ */
+typedef struct {
+    int dim;
+    int64_t n, ld;
+    const double *lo, *w, *V, *E;
+    const uint8_t *K, *A;
+} pg_regions_view;
+int pg_last_regions(const pg_context *ctx, pg_regions_view *out);
+
+/* ---- the steps of one iteration, on caller-supplied device arrays ---- */
+
+/*
+ * EVALUATE (Section 3.2): for each of n regions, V = the degree-7
+ * Genz-Malik rule, E = |R7 - R5| (its embedded degree-5 rule) and K = the
+ * axis of largest fourth divided difference (ties within 1e-10 of the
+ * maximum, or within 1e-12 of the size of the values entering the
+ * differences, go to the widest axis, then the lowest index). Inputs lo, w
+ * (ld >= n); outputs V[n], E[n], K[n]. Queued on the context's stream.
+ */
+int pg_evaluate(pg_context *ctx, const pg_integrand *f, int64_t n,
+                const double *lo, const double *w, int64_t ld, double *V,
+                double *E, uint8_t *K);
+
+/*
+ * TWO-LEVEL-ERROR + REL-ERR-CLASSIFY + the sums of Algorithm 2 on n
+ * regions. When `paired` is 1, n is even and regions i and i + n/2 are the
+ * halves of the parent whose estimate is Vp[i]; E is then refined in place
+ *   delta = |V_i + V_j - Vp| / 4, S = E_i + E_j,
+ *   E <- E (1 + 2 delta / S) + delta   (E + delta when S = 0).
+ * A[i] = 1 (active) iff E_i > rel_tol |V_i| (always 1 with relerr_filter 0).
+ * sums (host, 7 doubles): sum V, sum E, sum A V, sum A E, sum A, min E,
+ * max E. Blocks until the sums are known.
+ */
+int pg_classify(pg_context *ctx, int64_t n, int paired, const double *V,
+                double *E, const double *Vp, double rel_tol,
+                int relerr_filter, uint8_t *A, double *sums);
+
+/*
+ * THRESHOLD-CLASSIFY (Algorithm 3) on n regions with errors E and rel-err
+ * flags A_rel: searches t such that A = A_rel AND (E > t) finishes more than
+ * half of the regions with finished error <= P_max (tau |v_tot| - e_f),
+ * e_f = e_tot - e_it. P_max starts at 0.25 and, only under
+ * memory_pressure, grows by 0.10 per direction change (max 0.95). At most
+ * 64 trials and 10 direction changes. Returns 1 in *ok with t and A_out
+ * (device, n bytes) on success; 0 and A_out = A_rel on failure. Blocks.
+ */
+int pg_threshold_search(pg_context *ctx, int64_t n, const double *E,
+                        const uint8_t *A_rel, double v_tot, double e_tot,
+                        double e_it, double rel_tol, int memory_pressure,
+                        uint8_t *A_out, int *ok, double *t, int *trials);
+
+/*
+ * FILTER + parent update + SPLIT: stable compaction of the regions with
+ * A[i] = 1; the j-th survivor is bisected along axis K[i] into the lower
+ * half at index j and the upper half at index j + n_active of the output
+ * list (ld_out >= 2 n_active), and Vp[j] = V[i]. Writes *n_active (host).
+ * Blocks until *n_active is known.
+ */
+int pg_filter_split(pg_context *ctx, int dim, int64_t n, const double *lo,
+                    const double *w, int64_t ld_in, const uint8_t *K,
+                    const double *V, const uint8_t *A, double *lo_out,
+                    double *w_out, int64_t ld_out, double *Vp,
+                    int64_t *n_active);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PAGANI_H */

@@ -1,0 +1,279 @@
+"""Python front end of the PAGANI library: same operations as include/pagani.h.
+
+All arrays are PyTorch CUDA (HIP) tensors; work is queued on the current
+torch stream. Integrands are a family name plus a parameter vector (see
+include/pagani.h for the layouts).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+class PaganiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{L.STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _stream_handle(device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _integrand(family, d, params):
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    arr = (C.c_double * len(p))(*p.tolist())
+    f = L.Integrand(L.FAMILY_ID[family] if isinstance(family, str) else int(family),
+                    int(d), C.cast(arr, C.POINTER(C.c_double)), len(p))
+    return f, arr          # keep arr alive with f
+
+
+def _check_f64(t, name, device):
+    if not (isinstance(t, torch.Tensor) and t.dtype == torch.float64
+            and t.device == device and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float64 tensor on {device}")
+
+
+def _check_u8(t, name, device):
+    if not (isinstance(t, torch.Tensor) and t.dtype == torch.uint8
+            and t.device == device and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous uint8 tensor on {device}")
+
+
+@dataclass
+class IntegrateResult:
+    estimate: float
+    error: float
+    status: int
+    status_name: str
+    iterations: int
+    regions_evaluated: int
+    fevals: int
+    peak_regions: int
+    threshold_calls: int
+    threshold_trials: int
+    phase_ms: list
+    eval_launches: int
+
+
+class Context:
+    """A device workspace for region lists of up to `capacity` regions of up
+    to `dim_max` dimensions. The workspace is a torch uint8 tensor."""
+
+    def __init__(self, capacity: int = 1 << 22, dim_max: int = L.PG_DIM_MAX,
+                 device=None):
+        self.lib = L.load()
+        self.device = torch.device("cuda", torch.cuda.current_device()) \
+            if device is None else torch.device(device)
+        nbytes = self.lib.pg_workspace_bytes(dim_max, capacity)
+        if nbytes == 0:
+            raise ValueError("bad dim_max / capacity")
+        # 256-byte aligned view into a slightly larger tensor
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self._ws.data_ptr()) % 256
+        self.ws = self._ws[off:off + nbytes]
+        self.capacity, self.dim_max = capacity, dim_max
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = self.lib.pg_context_create(self.device.index, dim_max, capacity,
+                                            _ptr(self.ws), nbytes,
+                                            _stream_handle(self.device), C.byref(h))
+        if rc != 0:
+            raise PaganiError(rc, "pg_context_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pg_context_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- helpers ----------------------------------------------------------
+    def _bind_stream(self):
+        self.lib.pg_context_set_stream(self.h, _stream_handle(self.device))
+
+    def _soa_ld(self, lo, w):
+        """Leading dimension of a [d, n] structure-of-arrays pair."""
+        for t, nm in ((lo, "lo"), (w, "w")):
+            if not (t.dtype == torch.float64 and t.device == self.device
+                    and t.dim() == 2 and t.stride(1) == 1):
+                raise TypeError(f"{nm} must be a [d, n] float64 tensor on "
+                                f"{self.device} with unit column stride")
+        if lo.shape != w.shape:
+            raise TypeError("lo and w differ in shape")
+        d, n = lo.shape
+        ld = lo.stride(0) if d > 1 else n
+        if d > 1 and w.stride(0) != ld:
+            raise TypeError("lo and w must share their row stride")
+        return ld
+
+    def _err(self, rc):
+        return PaganiError(rc, self.lib.pg_last_error(self.h).decode())
+
+    # -- whole run -------------------------------------------------------
+    def integrate(self, family, d, params, lo=None, hi=None, rel_tol=1e-3,
+                  abs_tol=1e-20, init_splits=4, max_iters=100, relerr_filter=1,
+                  threshold_filter=1, max_regions=0, timing=False,
+                  trace_path=None) -> IntegrateResult:
+        """Algorithm 2 over the box [lo, hi] (default unit cube)."""
+        self._bind_stream()
+        f, keep = _integrand(family, d, params)
+        lo = np.zeros(d) if lo is None else np.asarray(lo, dtype=np.float64)
+        hi = np.ones(d) if hi is None else np.asarray(hi, dtype=np.float64)
+        clo = (C.c_double * d)(*lo.tolist())
+        chi = (C.c_double * d)(*hi.tolist())
+        o = L.Options()
+        self.lib.pg_default_options(C.byref(o))
+        o.rel_tol, o.abs_tol = float(rel_tol), float(abs_tol)
+        o.init_splits, o.max_iters = int(init_splits), int(max_iters)
+        o.relerr_filter, o.threshold_filter = int(relerr_filter), int(threshold_filter)
+        o.max_regions, o.timing = int(max_regions), int(bool(timing))
+        o.trace_path = trace_path.encode() if trace_path else None
+        r = L.Result()
+        with torch.cuda.device(self.device):
+            rc = self.lib.pg_integrate(self.h, C.byref(f), clo, chi, C.byref(o),
+                                       C.byref(r))
+        if rc < 0:
+            raise self._err(rc)
+        return IntegrateResult(**r.as_dict())
+
+    def integrate_workload(self, wl, **kw) -> IntegrateResult:
+        args = dict(rel_tol=wl.rel_tol, abs_tol=wl.abs_tol,
+                    init_splits=wl.init_splits, max_iters=wl.max_iters,
+                    relerr_filter=wl.relerr_filter,
+                    threshold_filter=wl.threshold_filter,
+                    max_regions=wl.max_regions)
+        args.update(kw)
+        return self.integrate(wl.family, wl.d, wl.params, wl.lo, wl.hi, **args)
+
+    def last_regions(self):
+        """The live list left by the last integrate(): dict of tensors viewing
+        the workspace (lo, w as [d, n]; V, E; K, A)."""
+        v = L.RegionsView()
+        rc = self.lib.pg_last_regions(self.h, C.byref(v))
+        if rc:
+            raise self._err(rc)
+        base = self.ws.data_ptr()
+
+        def view(ptr, nbytes, dtype):
+            off = ptr - base
+            return self.ws[off:off + nbytes].view(dtype)
+
+        d, n, ld = v.dim, v.n, v.ld
+        lo = view(v.lo, 8 * ld * d, torch.float64).view(d, ld)[:, :n]
+        w = view(v.w, 8 * ld * d, torch.float64).view(d, ld)[:, :n]
+        return dict(dim=d, n=n, lo=lo, w=w,
+                    V=view(v.V, 8 * n, torch.float64),
+                    E=view(v.E, 8 * n, torch.float64),
+                    K=view(v.K, n, torch.uint8), A=view(v.A, n, torch.uint8))
+
+    # -- the steps of one iteration ---------------------------------------
+    def evaluate(self, family, params, lo, w):
+        """EVALUATE on the boxes [lo, lo + w] (lo, w: [d, n] float64 tensors,
+        rows may be a strided view with unit element stride and a common row
+        stride). Returns (V, E, K)."""
+        self._bind_stream()
+        d, n = lo.shape
+        ld = self._soa_ld(lo, w)
+        V = torch.empty(n, dtype=torch.float64, device=self.device)
+        E = torch.empty_like(V)
+        K = torch.empty(n, dtype=torch.uint8, device=self.device)
+        f, keep = _integrand(family, d, params)
+        rc = self.lib.pg_evaluate(self.h, C.byref(f), n, _ptr(lo), _ptr(w), ld,
+                                  _ptr(V), _ptr(E), _ptr(K))
+        if rc:
+            raise self._err(rc)
+        return V, E, K
+
+    def classify(self, V, E, Vp=None, paired=False, rel_tol=1e-3, relerr_filter=1):
+        """TWO-LEVEL-ERROR (paired lists, in place on E) + REL-ERR-CLASSIFY.
+        Returns (A, sums) with sums = [sum V, sum E, sum AV, sum AE, sum A,
+        min E, max E]."""
+        self._bind_stream()
+        n = V.numel()
+        for t, nm in ((V, "V"), (E, "E")):
+            _check_f64(t, nm, self.device)
+        if paired:
+            _check_f64(Vp, "Vp", self.device)
+        A = torch.empty(n, dtype=torch.uint8, device=self.device)
+        sums = (C.c_double * 7)()
+        rc = self.lib.pg_classify(self.h, n, int(paired), _ptr(V), _ptr(E),
+                                  _ptr(Vp) if paired else None, float(rel_tol),
+                                  int(relerr_filter), _ptr(A), sums)
+        if rc:
+            raise self._err(rc)
+        return A, list(sums)
+
+    def threshold_search(self, E, A_rel, v_tot, e_tot, e_it, rel_tol,
+                         memory_pressure=False):
+        """THRESHOLD-CLASSIFY (Algorithm 3). Returns (ok, A, t, trials)."""
+        self._bind_stream()
+        _check_f64(E, "E", self.device)
+        _check_u8(A_rel, "A_rel", self.device)
+        A = torch.empty_like(A_rel)
+        ok, t, tr = C.c_int(), C.c_double(), C.c_int()
+        rc = self.lib.pg_threshold_search(self.h, E.numel(), _ptr(E), _ptr(A_rel),
+                                          float(v_tot), float(e_tot), float(e_it),
+                                          float(rel_tol), int(bool(memory_pressure)),
+                                          _ptr(A), C.byref(ok), C.byref(t),
+                                          C.byref(tr))
+        if rc:
+            raise self._err(rc)
+        return bool(ok.value), A, t.value, tr.value
+
+    def filter_split(self, lo, w, K, V, A):
+        """FILTER + parent update + SPLIT. Returns (lo2 [d, 2na], w2, Vp[na])."""
+        self._bind_stream()
+        d, n = lo.shape
+        ld = self._soa_ld(lo, w)
+        _check_u8(K, "K", self.device)
+        _check_u8(A, "A", self.device)
+        _check_f64(V, "V", self.device)
+        cap = max(2 * n, 2)
+        lo2 = torch.empty(d, cap, dtype=torch.float64, device=self.device)
+        w2 = torch.empty_like(lo2)
+        Vp = torch.empty(max(n, 1), dtype=torch.float64, device=self.device)
+        na = C.c_int64()
+        rc = self.lib.pg_filter_split(self.h, d, n, _ptr(lo), _ptr(w), ld, _ptr(K),
+                                      _ptr(V), _ptr(A), _ptr(lo2), _ptr(w2), cap,
+                                      _ptr(Vp), C.byref(na))
+        if rc:
+            raise self._err(rc)
+        m = na.value
+        return lo2[:, :2 * m].contiguous(), w2[:, :2 * m].contiguous(), Vp[:m].clone()
+
+
+_default_ctx = {}
+
+
+def context(capacity=1 << 22, dim_max=L.PG_DIM_MAX) -> Context:
+    """A cached context per (device, capacity, dim_max)."""
+    key = (torch.cuda.current_device(), capacity, dim_max)
+    if key not in _default_ctx:
+        _default_ctx[key] = Context(capacity, dim_max)
+    return _default_ctx[key]
+
+
+def integrate(family, d, params, lo=None, hi=None, capacity=1 << 22, **kw):
+    """One-call integration on the current device (see Context.integrate)."""
+    return context(capacity).integrate(family, d, params, lo, hi, **kw)

@@ -1,0 +1,772 @@
+// pg_api.hip -- host driver and C interface of the PAGANI library.
+//
+// pg_integrate runs Algorithm 2 of the paper: per iteration one EVALUATE
+// launch over the live list, one TWO-LEVEL + CLASSIFY launch with a
+// single-block reduce/scan, one 64-byte read-back for the termination test
+// and the threshold triggers, the threshold search of Algorithm 3 when it
+// is triggered (several candidate thresholds tested per pass over the list,
+// see search()), and one FILTER + SPLIT launch that writes the next list
+// into the other half of a ping-pong buffer. Nothing is allocated per
+// iteration; all buffers live in one workspace sized at context creation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pg_internal.hpp"
+
+using namespace pg;
+
+struct pg_context {
+    int device = 0;
+    hipStream_t stream = nullptr;            // nullptr: the null stream
+    int dim_max = 0;
+    int64_t cap = 0;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    bool own_ws = false;
+    double *lo[2] = {nullptr, nullptr}, *w[2] = {nullptr, nullptr};
+    double *V = nullptr, *E = nullptr, *Vp = nullptr;
+    uint8_t *K = nullptr, *A = nullptr, *A2 = nullptr;
+    SegPartials part{};
+    uint32_t *off = nullptr;
+    double *blk_cnt = nullptr, *blk_ae = nullptr;
+    Totals *dtot = nullptr, *htot = nullptr;
+    TrialTotals *dtrial = nullptr, *htrial = nullptr;
+    std::vector<hipEvent_t> events;
+    std::string err;
+    // live list left by the last pg_integrate
+    int last_cur = 0, last_dim = 0;
+    int64_t last_n = 0;
+};
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+
+struct Layout {
+    size_t lo[2], w[2], V, E, Vp, K, A, A2;
+    size_t pv, pe, pav, pae, pmin, pmax, pcnt, off;
+    size_t blk_cnt, blk_ae, dtot, dtrial, total;
+    int64_t nseg;
+};
+
+size_t bump(size_t &at, size_t bytes) {
+    at = (at + ALIGN - 1) / ALIGN * ALIGN;
+    const size_t r = at;
+    at += bytes;
+    return r;
+}
+
+Layout layout(int dim_max, int64_t cap) {
+    Layout L{};
+    size_t at = 0;
+    const size_t list = sizeof(double) * (size_t)dim_max * (size_t)cap;
+    for (int b = 0; b < 2; ++b) {
+        L.lo[b] = bump(at, list);
+        L.w[b] = bump(at, list);
+    }
+    L.V = bump(at, sizeof(double) * cap);
+    L.E = bump(at, sizeof(double) * cap);
+    L.Vp = bump(at, sizeof(double) * cap);
+    L.K = bump(at, cap);
+    L.A = bump(at, cap);
+    L.A2 = bump(at, cap);
+    L.nseg = 2 * ((cap + SEG - 1) / SEG) + 2;
+    L.pv = bump(at, sizeof(double) * L.nseg);
+    L.pe = bump(at, sizeof(double) * L.nseg);
+    L.pav = bump(at, sizeof(double) * L.nseg);
+    L.pae = bump(at, sizeof(double) * L.nseg);
+    L.pmin = bump(at, sizeof(double) * L.nseg);
+    L.pmax = bump(at, sizeof(double) * L.nseg);
+    L.pcnt = bump(at, sizeof(uint32_t) * L.nseg);
+    L.off = bump(at, sizeof(uint32_t) * L.nseg);
+    L.blk_cnt = bump(at, sizeof(double) * TRIAL_M * TRIAL_BLOCKS);
+    L.blk_ae = bump(at, sizeof(double) * TRIAL_M * TRIAL_BLOCKS);
+    L.dtot = bump(at, sizeof(Totals));
+    L.dtrial = bump(at, sizeof(TrialTotals));
+    L.total = (at + ALIGN - 1) / ALIGN * ALIGN;
+    return L;
+}
+
+int fail(pg_context *ctx, int code, const char *fmt, ...)
+    __attribute__((format(printf, 3, 4)));
+int fail(pg_context *ctx, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    return code;
+}
+
+#define HIP_OR_FAIL(ctx, expr)                                                 \
+    do {                                                                       \
+        hipError_t e_ = (expr);                                                \
+        if (e_ != hipSuccess)                                                  \
+            return fail(ctx, PG_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+int64_t npoints(int d) { return (int64_t(1) << d) + 2LL * d * d + 2LL * d + 1; }
+
+// Rule constants of the degree-7 rule and its degree-5 embedded rule per
+// orbit (weights relative to the box volume).
+Rule make_rule(int d) {
+    Rule R{};
+    const double D9 = 19683.0;
+    R.lam2 = std::sqrt(9.0 / 70.0);
+    R.lam3 = std::sqrt(9.0 / 10.0);
+    R.lam4 = std::sqrt(9.0 / 10.0);
+    R.lam5 = std::sqrt(9.0 / 19.0);
+    const double w7[5] = {(12824.0 - 9120.0 * d + 400.0 * d * d) / D9,
+                          980.0 / 6561.0, (1820.0 - 400.0 * d) / D9,
+                          200.0 / D9, 6859.0 / D9 / std::ldexp(1.0, d)};
+    const double w5[5] = {(729.0 - 950.0 * d + 50.0 * d * d) / 729.0,
+                          245.0 / 486.0, (265.0 - 100.0 * d) / 1458.0,
+                          25.0 / 729.0, 0.0};
+    for (int k = 0; k < 5; ++k) {
+        R.w7[k] = w7[k];
+        R.wn[k] = w7[k] - w5[k];
+    }
+    return R;
+}
+
+int make_params(pg_context *ctx, const pg_integrand *f, FParams *P) {
+    if (!f || !f->params) return fail(ctx, PG_EINVAL, "integrand is NULL");
+    const int d = f->dim;
+    if (d < PG_DIM_MIN || d > PG_DIM_MAX)
+        return fail(ctx, PG_EUNSUPPORTED, "dimension %d outside [%d, %d]", d,
+                    PG_DIM_MIN, PG_DIM_MAX);
+    if (d > ctx->dim_max)
+        return fail(ctx, PG_EINVAL, "dimension %d above the context's %d", d,
+                    ctx->dim_max);
+    int need;
+    switch (f->family) {
+    case PG_PRODUCT_PEAK: case PG_GAUSSIAN: need = 2 * d; break;
+    case PG_OSCILLATORY: need = d + 1; break;
+    case PG_CORNER_PEAK: case PG_MONOMIAL: need = d; break;
+    default: return fail(ctx, PG_EUNSUPPORTED, "unknown family %d", f->family);
+    }
+    if (f->n_params != need)
+        return fail(ctx, PG_EINVAL, "family %d in %d dimensions takes %d "
+                    "parameters, got %d", f->family, d, need, f->n_params);
+    if (!evaluate_supported(f->family, d))
+        return fail(ctx, PG_EUNSUPPORTED, "family %d, d = %d not built",
+                    f->family, d);
+    std::memset(P, 0, sizeof *P);
+    const double *p = f->params;
+    for (int k = 0; k < need; ++k)
+        if (!std::isfinite(p[k]))
+            return fail(ctx, PG_EINVAL, "parameter %d is not finite", k);
+    switch (f->family) {
+    case PG_PRODUCT_PEAK:
+        for (int k = 0; k < d; ++k) {
+            if (p[k] == 0.0) return fail(ctx, PG_EINVAL, "a_%d = 0", k);
+            P->p[k] = 1.0 / (p[k] * p[k]);
+            P->p[d + k] = p[d + k];
+        }
+        break;
+    case PG_GAUSSIAN:
+        for (int k = 0; k < d; ++k) {
+            P->p[k] = p[k] * p[k];
+            P->p[d + k] = p[d + k];
+        }
+        break;
+    case PG_OSCILLATORY:
+        for (int k = 0; k < d; ++k) P->p[k] = p[k];
+        P->p[d] = 2.0 * M_PI * p[d];
+        break;
+    default:
+        for (int k = 0; k < d; ++k) P->p[k] = p[k];
+        if (f->family == PG_MONOMIAL)
+            for (int k = 0; k < d; ++k)
+                if (p[k] < 0 || p[k] != std::floor(p[k]) || p[k] > 64)
+                    return fail(ctx, PG_EINVAL, "alpha_%d must be an integer "
+                                "in [0, 64]", k);
+        break;
+    }
+    return PG_OK;
+}
+
+// Waves per evaluation block: enough blocks x waves to cover the chip twice
+// over (256 CUs x 4 SIMDs x 2), at most the number of work units allows.
+int eval_waves(int d, int64_t n) {
+    const int64_t blocks = (n + 63) / 64;
+    const int64_t target = 2048;
+    int w = 1;
+    const int wmax = evaluate_max_waves(d);
+    while (w < wmax && blocks * w < target) w *= 2;
+    return w;
+}
+
+int sync_tot(pg_context *ctx, Totals *out) {
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->htot, ctx->dtot, sizeof(Totals),
+                                    hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+    *out = *ctx->htot;
+    return PG_OK;
+}
+
+// THRESHOLD-CLASSIFY (Algorithm 3) on the list (E, A_rel) of n regions. The
+// search is sequential -- each trial picks the next threshold from the
+// previous outcome -- but the thresholds it can reach in the next
+// TRIAL_DEPTH trials form a binary tree that depends only on the current
+// threshold and min/max E, so one pass over the list tests all of them and
+// the host then walks the tree exactly as the sequential search would.
+struct SearchOut {
+    int ok = 0, trials = 0;
+    double t = -HUGE_VAL;
+};
+
+int search(pg_context *ctx, int64_t n, const double *E, const uint8_t *A_rel,
+           double v_tot, double e_tot, double e_it, double tau, int mem,
+           double mn, double mx, SearchOut *out) {
+    const double e_b = e_tot - tau * std::fabs(v_tot);
+    const double allowance = e_it - e_b;      // = tau |v_tot| - e_f
+    double P_max = 0.25;
+    double t = e_it / (double)n;
+    int last_dir = 0, dir_changes = 0, trials = 0;
+    double thr[TRIAL_M];
+    *out = SearchOut{};
+    for (;;) {
+        thr[0] = t;
+        for (int i = 0; 2 * i + 2 < TRIAL_M; ++i) {
+            thr[2 * i + 1] = thr[i] + (mx - thr[i]) / 2.0;     // raise
+            thr[2 * i + 2] = thr[i] - (thr[i] - mn) / 2.0;     // lower
+        }
+        HIP_OR_FAIL(ctx, launch_trials(ctx->stream, n, E, A_rel, thr,
+                                       ctx->blk_cnt, ctx->blk_ae,
+                                       ctx->dtrial));
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->htrial, ctx->dtrial,
+                                        sizeof(TrialTotals),
+                                        hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+        const TrialTotals &T = *ctx->htrial;
+        int node = 0;
+        for (int level = 0; level < TRIAL_DEPTH; ++level) {
+            if (trials >= 64) { out->trials = trials; return PG_OK; }
+            const double tt = thr[node];
+            ++trials;
+            const double s_abar = (double)n - T.cnt[node];
+            const double e_abar = e_it - T.ae[node];
+            int dir;
+            if (s_abar > 0.5 * (double)n) {
+                if (e_abar <= P_max * allowance) {
+                    out->ok = 1;
+                    out->t = tt;
+                    out->trials = trials;
+                    return PG_OK;
+                }
+                dir = -1;                         // accuracy failed: lower t
+            } else {
+                dir = +1;                         // memory failed: raise t
+            }
+            if (last_dir != 0 && dir != last_dir) {
+                ++dir_changes;
+                if (mem) P_max = std::min(P_max + 0.10, 0.95);
+                if (dir_changes >= 10) { out->trials = trials; return PG_OK; }
+            }
+            last_dir = dir;
+            t = dir > 0 ? tt + (mx - tt) / 2.0 : tt - (tt - mn) / 2.0;
+            node = dir > 0 ? 2 * node + 1 : 2 * node + 2;
+        }
+    }
+}
+
+int validate_list(pg_context *ctx, int64_t n, int64_t ld) {
+    if (n < 0) return fail(ctx, PG_EINVAL, "n = %lld < 0", (long long)n);
+    if (ld < n) return fail(ctx, PG_EINVAL, "ld %lld < n %lld", (long long)ld,
+                            (long long)n);
+    if (n > ctx->cap)
+        return fail(ctx, PG_ENOMEM, "n = %lld above the context capacity %lld",
+                    (long long)n, (long long)ctx->cap);
+    return PG_OK;
+}
+
+struct TraceRec {
+    int64_t it, n, n_active;
+    int32_t thr_invoked, thr_ok, thr_trials, terminal;
+    double t, v, e, v_f, e_f;
+};
+
+}  // namespace
+
+extern "C" {
+
+void pg_default_options(pg_options *opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof *opt);
+    opt->rel_tol = 1e-3;
+    opt->abs_tol = 1e-20;
+    opt->init_splits = 4;
+    opt->max_iters = 100;
+    opt->relerr_filter = 1;
+    opt->threshold_filter = 1;
+}
+
+size_t pg_workspace_bytes(int dim_max, int64_t capacity) {
+    if (dim_max < PG_DIM_MIN || dim_max > PG_DIM_MAX || capacity < 2) return 0;
+    return layout(dim_max, capacity).total;
+}
+
+int pg_context_create(int device, int dim_max, int64_t capacity,
+                      void *workspace, size_t ws_bytes, void *stream,
+                      pg_context **out) {
+    if (!out) return PG_EINVAL;
+    *out = nullptr;
+    if (dim_max < PG_DIM_MIN || dim_max > PG_DIM_MAX) return PG_EINVAL;
+    if (capacity < 2 || capacity > (int64_t(1) << 31)) return PG_EINVAL;
+    const Layout L = layout(dim_max, capacity);
+    if (workspace && ws_bytes < L.total) return PG_ENOMEM;
+    if (workspace && (reinterpret_cast<uintptr_t>(workspace) % ALIGN))
+        return PG_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return PG_EHIP;
+    pg_context *ctx = new pg_context();
+    ctx->device = device;
+    ctx->dim_max = dim_max;
+    ctx->cap = capacity;
+    if (workspace) {
+        ctx->ws = workspace;
+        ctx->ws_bytes = ws_bytes;
+    } else {
+        if (hipMalloc(&ctx->ws, L.total) != hipSuccess) {
+            delete ctx;
+            return PG_ENOMEM;
+        }
+        ctx->ws_bytes = L.total;
+        ctx->own_ws = true;
+    }
+    ctx->stream = (hipStream_t)stream;      // NULL: the null stream
+    if (hipHostMalloc((void **)&ctx->htot, sizeof(Totals), 0) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->htrial, sizeof(TrialTotals), 0) !=
+            hipSuccess) {
+        pg_context_destroy(ctx);
+        return PG_ENOMEM;
+    }
+    char *b = (char *)ctx->ws;
+    for (int q = 0; q < 2; ++q) {
+        ctx->lo[q] = (double *)(b + L.lo[q]);
+        ctx->w[q] = (double *)(b + L.w[q]);
+    }
+    ctx->V = (double *)(b + L.V);
+    ctx->E = (double *)(b + L.E);
+    ctx->Vp = (double *)(b + L.Vp);
+    ctx->K = (uint8_t *)(b + L.K);
+    ctx->A = (uint8_t *)(b + L.A);
+    ctx->A2 = (uint8_t *)(b + L.A2);
+    ctx->part.v = (double *)(b + L.pv);
+    ctx->part.e = (double *)(b + L.pe);
+    ctx->part.av = (double *)(b + L.pav);
+    ctx->part.ae = (double *)(b + L.pae);
+    ctx->part.emin = (double *)(b + L.pmin);
+    ctx->part.emax = (double *)(b + L.pmax);
+    ctx->part.cnt = (uint32_t *)(b + L.pcnt);
+    ctx->off = (uint32_t *)(b + L.off);
+    ctx->blk_cnt = (double *)(b + L.blk_cnt);
+    ctx->blk_ae = (double *)(b + L.blk_ae);
+    ctx->dtot = (Totals *)(b + L.dtot);
+    ctx->dtrial = (TrialTotals *)(b + L.dtrial);
+    *out = ctx;
+    return PG_OK;
+}
+
+void pg_context_destroy(pg_context *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
+    if (ctx->htot) (void)hipHostFree(ctx->htot);
+    if (ctx->htrial) (void)hipHostFree(ctx->htrial);
+    if (ctx->own_ws && ctx->ws) (void)hipFree(ctx->ws);
+    delete ctx;
+}
+
+int pg_context_set_stream(pg_context *ctx, void *stream) {
+    if (!ctx) return PG_EINVAL;
+    ctx->stream = (hipStream_t)stream;
+    return PG_OK;
+}
+
+const char *pg_last_error(const pg_context *ctx) {
+    return ctx ? ctx->err.c_str() : "no context";
+}
+
+int pg_evaluate(pg_context *ctx, const pg_integrand *f, int64_t n,
+                const double *lo, const double *w, int64_t ld, double *V,
+                double *E, uint8_t *K) {
+    if (!ctx) return PG_EINVAL;
+    FParams P;
+    int rc = make_params(ctx, f, &P);
+    if (rc) return rc;
+    if (ld < n || n < 0) return fail(ctx, PG_EINVAL, "bad n / ld");
+    if (n == 0) return PG_OK;
+    if (!lo || !w || !V || !E || !K)
+        return fail(ctx, PG_EINVAL, "NULL array");
+    HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+    const Rule R = make_rule(f->dim);
+    HIP_OR_FAIL(ctx, launch_evaluate(ctx->stream, f->family, f->dim, P, R, n,
+                                     lo, w, ld, V, E, K,
+                                     eval_waves(f->dim, n)));
+    return PG_OK;
+}
+
+int pg_classify(pg_context *ctx, int64_t n, int paired, const double *V,
+                double *E, const double *Vp, double rel_tol,
+                int relerr_filter, uint8_t *A, double *sums) {
+    if (!ctx) return PG_EINVAL;
+    int rc = validate_list(ctx, n, n);
+    if (rc) return rc;
+    if (paired && (n % 2)) return fail(ctx, PG_EINVAL, "paired list of odd n");
+    if (!V || !E || !A || !sums || (paired && !Vp))
+        return fail(ctx, PG_EINVAL, "NULL array");
+    if (n == 0) {
+        for (int k = 0; k < 7; ++k) sums[k] = 0.0;
+        sums[5] = HUGE_VAL;
+        sums[6] = -HUGE_VAL;
+        return PG_OK;
+    }
+    HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+    HIP_OR_FAIL(ctx, launch_classify(ctx->stream, n, paired ? 1 : 0, V, E, Vp,
+                                     rel_tol, relerr_filter, A, ctx->part));
+    HIP_OR_FAIL(ctx, launch_reduce_scan(ctx->stream, seg_count(n, paired),
+                                        ctx->part, ctx->off, ctx->dtot));
+    Totals T;
+    rc = sync_tot(ctx, &T);
+    if (rc) return rc;
+    sums[0] = T.v; sums[1] = T.e; sums[2] = T.av; sums[3] = T.ae;
+    sums[4] = T.cnt; sums[5] = T.emin; sums[6] = T.emax;
+    return PG_OK;
+}
+
+int pg_threshold_search(pg_context *ctx, int64_t n, const double *E,
+                        const uint8_t *A_rel, double v_tot, double e_tot,
+                        double e_it, double rel_tol, int memory_pressure,
+                        uint8_t *A_out, int *ok, double *t, int *trials) {
+    if (!ctx) return PG_EINVAL;
+    int rc = validate_list(ctx, n, n);
+    if (rc) return rc;
+    if (n == 0 || !E || !A_rel || !A_out || !ok || !t || !trials)
+        return fail(ctx, PG_EINVAL, "empty list or NULL argument");
+    HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+    // min / max of E over the whole list (the count pass over E records them)
+    HIP_OR_FAIL(ctx, launch_seg_count(ctx->stream, n, 0, -HUGE_VAL, E, E,
+                                      A_rel, ctx->part));
+    HIP_OR_FAIL(ctx, launch_reduce_scan(ctx->stream, seg_count(n, 0),
+                                        ctx->part, ctx->off, ctx->dtot));
+    Totals T;
+    rc = sync_tot(ctx, &T);
+    if (rc) return rc;
+    SearchOut so;
+    rc = search(ctx, n, E, A_rel, v_tot, e_tot, e_it, rel_tol,
+                memory_pressure, T.emin, T.emax, &so);
+    if (rc) return rc;
+    *ok = so.ok;
+    *t = so.ok ? so.t : NAN;
+    *trials = so.trials;
+    HIP_OR_FAIL(ctx, launch_apply_threshold(ctx->stream, n,
+                                            so.ok ? so.t : -HUGE_VAL, A_rel,
+                                            E, A_out));
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+    return PG_OK;
+}
+
+int pg_filter_split(pg_context *ctx, int dim, int64_t n, const double *lo,
+                    const double *w, int64_t ld_in, const uint8_t *K,
+                    const double *V, const uint8_t *A, double *lo_out,
+                    double *w_out, int64_t ld_out, double *Vp,
+                    int64_t *n_active) {
+    if (!ctx) return PG_EINVAL;
+    if (dim < PG_DIM_MIN || dim > PG_DIM_MAX)
+        return fail(ctx, PG_EINVAL, "dimension %d", dim);
+    int rc = validate_list(ctx, n, ld_in);
+    if (rc) return rc;
+    if (!n_active) return fail(ctx, PG_EINVAL, "n_active is NULL");
+    *n_active = 0;
+    if (n == 0) return PG_OK;
+    if (!lo || !w || !K || !V || !A || !lo_out || !w_out || !Vp)
+        return fail(ctx, PG_EINVAL, "NULL array");
+    HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+    HIP_OR_FAIL(ctx, launch_seg_count(ctx->stream, n, 0, 0.0, V, nullptr, A,
+                                      ctx->part));
+    HIP_OR_FAIL(ctx, launch_reduce_scan(ctx->stream, seg_count(n, 0),
+                                        ctx->part, ctx->off, ctx->dtot));
+    Totals T;
+    rc = sync_tot(ctx, &T);
+    if (rc) return rc;
+    const int64_t na = (int64_t)T.cnt;
+    if (ld_out < 2 * na)
+        return fail(ctx, PG_EINVAL, "ld_out %lld < 2 n_active %lld",
+                    (long long)ld_out, (long long)(2 * na));
+    HIP_OR_FAIL(ctx, launch_compact_split(ctx->stream, dim, n, 0, 0.0, A,
+                                          nullptr, V, K, lo, w, ld_in,
+                                          ctx->off, na, lo_out, w_out, ld_out,
+                                          Vp));
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+    *n_active = na;
+    return PG_OK;
+}
+
+int pg_last_regions(const pg_context *ctx, pg_regions_view *out) {
+    if (!ctx || !out) return PG_EINVAL;
+    out->dim = ctx->last_dim;
+    out->n = ctx->last_n;
+    out->ld = ctx->cap;
+    out->lo = ctx->lo[ctx->last_cur];
+    out->w = ctx->w[ctx->last_cur];
+    out->V = ctx->V;
+    out->E = ctx->E;
+    out->K = ctx->K;
+    out->A = ctx->A;
+    return PG_OK;
+}
+
+int pg_integrate(pg_context *ctx, const pg_integrand *f, const double *lo,
+                 const double *hi, const pg_options *opt, pg_result *out) {
+    if (!ctx) return PG_EINVAL;
+    pg_result res;
+    std::memset(&res, 0, sizeof res);
+    res.estimate = NAN;
+    res.error = NAN;
+    if (out) *out = res;
+    ctx->err.clear();
+    pg_options o;
+    if (opt) o = *opt;
+    else pg_default_options(&o);
+    FParams P;
+    int rc = make_params(ctx, f, &P);
+    if (rc) return rc;
+    const int d = f->dim;
+    if (!lo || !hi) return fail(ctx, PG_EINVAL, "bounds are NULL");
+    for (int k = 0; k < d; ++k)
+        if (!(lo[k] < hi[k]) || !std::isfinite(lo[k]) || !std::isfinite(hi[k]))
+            return fail(ctx, PG_EINVAL, "empty or infinite range on axis %d", k);
+    if (!(o.rel_tol > 0.0) && !(o.abs_tol > 0.0))
+        return fail(ctx, PG_EINVAL, "no positive tolerance");
+    if (o.init_splits < 1) return fail(ctx, PG_EINVAL, "init_splits < 1");
+    if (o.max_iters < 1) return fail(ctx, PG_EINVAL, "max_iters < 1");
+    const int64_t cap = o.max_regions > 0 ? o.max_regions : ctx->cap;
+    if (cap > ctx->cap)
+        return fail(ctx, PG_ENOMEM, "max_regions %lld above the capacity %lld",
+                    (long long)cap, (long long)ctx->cap);
+    int64_t n = 1;
+    for (int k = 0; k < d; ++k) {
+        n *= o.init_splits;
+        if (n > cap)
+            return fail(ctx, PG_EINVAL, "initial grid %d^%d above the cap %lld",
+                        o.init_splits, d, (long long)cap);
+    }
+    HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+    const Rule R = make_rule(d);
+    const double tau = o.rel_tol;
+    const int64_t ld = ctx->cap;
+    hipStream_t st = ctx->stream;
+
+    FILE *tr = nullptr;
+    std::vector<uint8_t> hK, hA;
+    std::vector<double> hE;
+    if (o.trace_path) {
+        tr = std::fopen(o.trace_path, "wb");
+        if (!tr) return fail(ctx, PG_EINVAL, "cannot open %s", o.trace_path);
+        const char magic[8] = {'P', 'G', 'T', 'R', 'A', 'C', 'E', '1'};
+        const int32_t hd[2] = {d, f->family};
+        const int64_t zero[2] = {0, 0};
+        std::fwrite(magic, 1, 8, tr);
+        std::fwrite(hd, 4, 2, tr);
+        std::fwrite(zero, 8, 2, tr);
+    }
+    // timing events: 5 per iteration
+    const bool timing = o.timing != 0;
+    if (timing) {
+        const size_t need = 5 * (size_t)o.max_iters;
+        while (ctx->events.size() < need) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) {
+                if (tr) std::fclose(tr);
+                return fail(ctx, PG_EHIP, "hipEventCreate failed");
+            }
+            ctx->events.push_back(e);
+        }
+    }
+#define RUN_FAIL(expr)                                                         \
+    do {                                                                       \
+        hipError_t e_ = (expr);                                                \
+        if (e_ != hipSuccess) {                                                \
+            if (tr) std::fclose(tr);                                           \
+            return fail(ctx, PG_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+        }                                                                      \
+    } while (0)
+#define RUN_RC(expr)                                                           \
+    do {                                                                       \
+        int rc_ = (expr);                                                      \
+        if (rc_) {                                                             \
+            if (tr) std::fclose(tr);                                           \
+            return rc_;                                                        \
+        }                                                                      \
+    } while (0)
+
+    {
+        double a[PG_DIM_MAX], width[PG_DIM_MAX];
+        for (int k = 0; k < d; ++k) {
+            a[k] = lo[k];
+            width[k] = (hi[k] - lo[k]) / (double)o.init_splits;
+        }
+        RUN_FAIL(launch_init(st, d, o.init_splits, a, width, ctx->lo[0],
+                             ctx->w[0], ld));
+    }
+    int cur = 0;
+    double v_f = 0.0, e_f = 0.0, v_tot = 0.0, e_tot = 0.0, prev_vtot = NAN;
+    int status = PG_MAX_ITERS;
+    int it;
+    res.peak_regions = n;
+    int nev = 0;
+    for (it = 1; it <= o.max_iters; ++it) {
+        const int paired = it > 1;
+        hipEvent_t *ev = timing ? &ctx->events[5 * (it - 1)] : nullptr;
+        if (timing) RUN_FAIL(hipEventRecord(ev[0], st));
+        RUN_FAIL(launch_evaluate(st, f->family, d, P, R, n, ctx->lo[cur],
+                                 ctx->w[cur], ld, ctx->V, ctx->E, ctx->K,
+                                 eval_waves(d, n)));
+        ++nev;
+        if (timing) RUN_FAIL(hipEventRecord(ev[1], st));
+        res.regions_evaluated += n;
+        RUN_FAIL(launch_classify(st, n, paired, ctx->V, ctx->E, ctx->Vp, tau,
+                                 o.relerr_filter, ctx->A, ctx->part));
+        const int64_t nseg = seg_count(n, paired);
+        RUN_FAIL(launch_reduce_scan(st, nseg, ctx->part, ctx->off, ctx->dtot));
+        if (timing) RUN_FAIL(hipEventRecord(ev[2], st));
+        Totals T;
+        RUN_RC(sync_tot(ctx, &T));
+        const double v = T.v, e = T.e;
+        v_tot = v + v_f;
+        e_tot = e + e_f;
+        TraceRec rec{};
+        rec.it = it;
+        rec.n = n;
+        rec.terminal = -1;
+        rec.t = NAN;
+        rec.v = v;
+        rec.e = e;
+        rec.v_f = v_f;
+        rec.e_f = e_f;
+        const bool terminated =
+            (e_tot <= tau * std::fabs(v_tot)) || (e_tot <= o.abs_tol);
+        double av = T.av, ae = T.ae;
+        int64_t n_act = (int64_t)T.cnt;
+        const int64_t n_rel = n_act;
+        SearchOut so;
+        if (terminated) {
+            status = PG_OK;
+            rec.terminal = PG_OK;
+        } else {
+            const bool trig_a = o.threshold_filter && it >= 2 &&
+                                std::fabs(v_tot - prev_vtot) <=
+                                    tau * std::fabs(v_tot);
+            const bool trig_b = o.threshold_filter && 2 * n_rel > cap;
+            if (trig_a || trig_b) {
+                ++res.threshold_calls;
+                rec.thr_invoked = 1;
+                RUN_RC(search(ctx, n, ctx->E, ctx->A, v_tot, e_tot, e, tau,
+                              trig_b ? 1 : 0, T.emin, T.emax, &so));
+                res.threshold_trials += so.trials;
+                rec.thr_ok = so.ok;
+                rec.thr_trials = so.trials;
+                if (so.ok) {
+                    rec.t = so.t;
+                    RUN_FAIL(launch_seg_count(st, n, paired, so.t, ctx->V,
+                                              ctx->E, ctx->A, ctx->part));
+                    RUN_FAIL(launch_reduce_scan(st, nseg, ctx->part, ctx->off,
+                                                ctx->dtot));
+                    Totals T2;
+                    RUN_RC(sync_tot(ctx, &T2));
+                    av = T2.av;
+                    ae = T2.ae;
+                    n_act = (int64_t)T2.cnt;
+                }
+            }
+            if (!so.ok && 2 * n_rel > cap) {
+                status = PG_MEMORY_EXHAUSTED;
+                rec.terminal = status;
+            }
+        }
+        if (timing) RUN_FAIL(hipEventRecord(ev[3], st));
+        if (rec.terminal < 0) {
+            prev_vtot = v_tot;
+            if (n_act == 0) {
+                status = PG_NO_ACTIVE;
+                rec.terminal = status;
+            } else if (it == o.max_iters) {
+                status = PG_MAX_ITERS;
+                rec.terminal = status;
+            }
+        }
+        rec.n_active = rec.terminal == PG_OK ? n_rel : n_act;
+        if (tr) {
+            hK.resize(n);
+            hA.resize(n);
+            RUN_FAIL(hipMemcpyAsync(hK.data(), ctx->K, n, hipMemcpyDeviceToHost, st));
+            RUN_FAIL(hipMemcpyAsync(hA.data(), ctx->A, n, hipMemcpyDeviceToHost, st));
+            if (so.ok) {
+                hE.resize(n);
+                RUN_FAIL(hipMemcpyAsync(hE.data(), ctx->E, n * sizeof(double),
+                                        hipMemcpyDeviceToHost, st));
+            }
+            RUN_FAIL(hipStreamSynchronize(st));
+            if (so.ok)
+                for (int64_t i = 0; i < n; ++i)
+                    hA[i] = (uint8_t)(hA[i] && hE[i] > so.t);
+            std::fwrite(&rec, sizeof rec, 1, tr);
+            std::fwrite(hK.data(), 1, n, tr);
+            std::fwrite(hA.data(), 1, n, tr);
+        }
+        if (rec.terminal >= 0) {
+            if (timing) RUN_FAIL(hipEventRecord(ev[4], st));
+            break;
+        }
+        v_f = v - av + v_f;
+        e_f = e - ae + e_f;
+        RUN_FAIL(launch_compact_split(st, d, n, paired, so.ok ? so.t : 0.0,
+                                      ctx->A, so.ok ? ctx->E : nullptr, ctx->V,
+                                      ctx->K, ctx->lo[cur], ctx->w[cur], ld,
+                                      ctx->off, n_act, ctx->lo[1 - cur],
+                                      ctx->w[1 - cur], ld, ctx->Vp));
+        if (timing) RUN_FAIL(hipEventRecord(ev[4], st));
+        cur = 1 - cur;
+        n = 2 * n_act;
+        res.peak_regions = std::max<int64_t>(res.peak_regions, n);
+    }
+    if (it > o.max_iters) it = o.max_iters;
+    RUN_FAIL(hipStreamSynchronize(st));
+    if (tr) std::fclose(tr);
+    tr = nullptr;
+    if (timing) {
+        for (int q = 0; q < it; ++q) {
+            hipEvent_t *ev = &ctx->events[5 * q];
+            float ms;
+            for (int ph = 0; ph < 4; ++ph) {
+                if (hipEventElapsedTime(&ms, ev[ph], ev[ph + 1]) == hipSuccess)
+                    res.phase_ms[ph] += ms;
+            }
+        }
+    }
+    ctx->last_cur = cur;
+    ctx->last_n = n;
+    ctx->last_dim = d;
+    res.estimate = v_tot;
+    res.error = e_tot;
+    res.status = status;
+    res.iterations = it;
+    res.fevals = res.regions_evaluated * npoints(d);
+    res.eval_launches = nev;
+    if (out) *out = res;
+    return status;
+#undef RUN_FAIL
+#undef RUN_RC
+}
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+// pg_internal.hpp -- types and launchers shared by the kernels and the host
+// driver of the PAGANI library (gfx950). Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "pagani.h"
+
+namespace pg {
+
+// Regions handled by one block of the list kernels (classify, threshold
+// count, compact + split). A segment is a contiguous run of at most SEG
+// regions; segments never straddle the two halves of a paired list.
+constexpr int SEG = 2048;
+constexpr int LIST_THREADS = 256;
+// Blocks of the threshold-trial pass (grid-stride, fixed for determinism).
+constexpr int TRIAL_BLOCKS = 1024;
+// Thresholds tested per trial pass: a complete binary tree of depth 4 of the
+// search's possible next steps.
+constexpr int TRIAL_DEPTH = 4;
+constexpr int TRIAL_M = (1 << TRIAL_DEPTH) - 1;
+// Threads of the single-block reduce/scan kernels.
+constexpr int SCAN_THREADS = 1024;
+
+// Integrand parameters as the kernels take them (by value, in SGPRs):
+//  product peak: p[k] = a_k^-2, p[d+k] = u_k
+//  gaussian:     p[k] = a_k^2,  p[d+k] = u_k
+//  oscillatory:  p[k] = a_k,    p[d]   = 2 pi u_1
+//  corner peak:  p[k] = a_k
+//  monomial:     p[k] = alpha_k
+struct FParams {
+    double p[2 * PG_DIM_MAX + 2];
+};
+
+// Per-dimension rule constants: generators lambda2..5 and the weights of
+// the degree-7 rule (w7) and of the null rule (wn = w7 - w5) per orbit.
+struct Rule {
+    double lam2, lam3, lam4, lam5;
+    double w7[5];
+    double wn[5];
+};
+
+// Segment geometry of a list of n regions (paired: two halves of n/2).
+__host__ __device__ inline int64_t seg_count(int64_t n, int paired) {
+    if (n <= 0) return 0;
+    if (!paired) return (n + SEG - 1) / SEG;
+    int64_t half = n / 2;
+    return 2 * ((half + SEG - 1) / SEG);
+}
+__host__ __device__ inline void seg_range(int64_t s, int64_t n, int paired,
+                                          int64_t *start, int64_t *end) {
+    if (!paired) {
+        *start = s * SEG;
+        *end = (*start + SEG < n) ? *start + SEG : n;
+        return;
+    }
+    int64_t half = n / 2;
+    int64_t nh = (half + SEG - 1) / SEG;
+    int64_t base = 0, j = s;
+    if (s >= nh) { base = half; j = s - nh; }
+    *start = base + j * SEG;
+    int64_t e = (j + 1) * SEG;
+    *end = base + (e < half ? e : half);
+}
+
+// Per-segment partial results written by the list kernels.
+struct SegPartials {
+    double *v, *e, *av, *ae, *emin, *emax;
+    uint32_t *cnt;
+};
+
+// Totals of a list pass, read back by the host.
+struct Totals {
+    double v, e, av, ae, emin, emax;
+    double cnt;      // number of active regions (exact as a double < 2^53)
+    double pad;
+};
+
+// Per-candidate sums of one threshold trial pass.
+struct TrialTotals {
+    double cnt[TRIAL_M];   // active regions under each candidate threshold
+    double ae[TRIAL_M];    // sum of E over those regions
+};
+
+// ---- launchers (pg_kernels.hip); all queue on `st` -----------------------
+hipError_t launch_init(hipStream_t st, int d, int g, const double *a,
+                       const double *width, double *lo, double *w,
+                       int64_t ld);
+// waves: waves per block (1..16), block covers 64 regions.
+hipError_t launch_evaluate(hipStream_t st, int family, int d,
+                           const FParams &P, const Rule &R, int64_t n,
+                           const double *lo, const double *w, int64_t ld,
+                           double *V, double *E, uint8_t *K, int waves);
+bool evaluate_supported(int family, int d);
+int evaluate_max_waves(int d);
+hipError_t launch_classify(hipStream_t st, int64_t n, int paired,
+                           const double *V, double *E, const double *Vp,
+                           double tau, int relerr, uint8_t *A,
+                           SegPartials part);
+hipError_t launch_seg_count(hipStream_t st, int64_t n, int paired, double t,
+                            const double *V, const double *E,
+                            const uint8_t *A_rel, SegPartials part);
+hipError_t launch_reduce_scan(hipStream_t st, int64_t nseg, SegPartials part,
+                              uint32_t *offsets, Totals *tot);
+hipError_t launch_trials(hipStream_t st, int64_t n, const double *E,
+                         const uint8_t *A_rel, const double *thr,
+                         double *blk_cnt, double *blk_ae, TrialTotals *tot);
+hipError_t launch_compact_split(hipStream_t st, int d, int64_t n, int paired,
+                                double t, const uint8_t *A_rel,
+                                const double *E, const double *V,
+                                const uint8_t *K, const double *lo,
+                                const double *w, int64_t ld_in,
+                                const uint32_t *offsets, int64_t n_active,
+                                double *lo_out, double *w_out, int64_t ld_out,
+                                double *Vp);
+hipError_t launch_apply_threshold(hipStream_t st, int64_t n, double t,
+                                  const uint8_t *A_rel, const double *E,
+                                  uint8_t *A_out);
+
+}  // namespace pg

@@ -1,0 +1,693 @@
+// pg_kernels.hip -- gfx950 kernels of one PAGANI iteration (Algorithm 2).
+//
+// EVALUATE is FP64-VALU bound: one lane owns one region for the whole
+// cubature rule (64 regions per block), so the rule's weighted sums need no
+// cross-lane reduction. The point set is cut into work units of four points
+// (one axis: +-lambda2, +-lambda3; one pair of axes: four sign choices of
+// lambda4; four sign vectors of lambda5); W waves of a block share the same
+// 64 regions and take every W-th unit, so small lists still fill the chip.
+// The unit index is wave-uniform: which coordinates move, and with what
+// sign, is decided in scalar registers, and every lane builds its point with
+// one FMA per coordinate, x_k = c_k + s_k (lambda h_k), s_k in {-1, 0, 1},
+// which rounds exactly like c_k + s_k * (lambda * h_k).
+//
+// The list kernels (classify, threshold trials, count, compact + split) are
+// HBM bound; they stream SoA arrays with coalesced accesses and reduce in a
+// fixed order (no floating-point atomics), so runs are bit-reproducible.
+#include "pg_internal.hpp"
+
+#include <hip/hip_runtime.h>
+
+namespace pg {
+
+// ---------------------------------------------------------------------------
+// Integrands (parameter layout: see FParams). Inlined into the evaluation.
+// ---------------------------------------------------------------------------
+template <int FAM, int D>
+__device__ __forceinline__ double integrand(const double *x, const FParams &P) {
+    if constexpr (FAM == PG_PRODUCT_PEAK) {
+        double den = 1.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const double t = x[k] - P.p[D + k];
+            den *= fma(t, t, P.p[k]);
+        }
+        return 1.0 / den;
+    } else if constexpr (FAM == PG_GAUSSIAN) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const double t = x[k] - P.p[D + k];
+            s = fma(P.p[k] * t, t, s);
+        }
+        return exp(-s);
+    } else if constexpr (FAM == PG_OSCILLATORY) {
+        double s = P.p[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) s = fma(P.p[k], x[k], s);
+        return cos(s);
+    } else if constexpr (FAM == PG_CORNER_PEAK) {
+        double s = 1.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) s = fma(P.p[k], x[k], s);
+        double pw = s;
+#pragma unroll
+        for (int e = 0; e < D; ++e) pw *= s;   // s^(D+1)
+        return 1.0 / pw;
+    } else {                                     // monomial (test family)
+        double r = 1.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const int e = (int)P.p[k];
+            for (int j = 0; j < e; ++j) r *= x[k];
+        }
+        return r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// EVALUATE
+// ---------------------------------------------------------------------------
+constexpr int EVAL_MAX_WAVES = 8;
+
+template <int FAM, int D>
+__global__ void __launch_bounds__(64 * EVAL_MAX_WAVES)
+k_evaluate(const FParams P, const Rule R, int64_t n,
+           const double *__restrict__ lo, const double *__restrict__ wid,
+           int64_t ld, double *__restrict__ V, double *__restrict__ E,
+           uint8_t *__restrict__ K) {
+    constexpr int NPAIR = D * (D - 1) / 2;
+    constexpr int N5 = (1 << D) / 4;         // units of four orbit-5 points
+    constexpr int U = D + NPAIR + N5;
+    extern __shared__ double lds[];          // Dbuf[D][64], part[W][5][64]
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int W = blockDim.x >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t r = r0 < n ? r0 : n - 1;   // tail lanes recompute the last
+
+    double c[D], h[D], l4[D], l5[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        h[k] = wid[k * ld + r] * 0.5;
+        c[k] = lo[k * ld + r] + h[k];
+        l4[k] = R.lam4 * h[k];
+        l5[k] = R.lam5 * h[k];
+    }
+
+    double fc = 0.0;
+    if (wave < D) fc = integrand<FAM, D>(c, P);   // axis units need f(c)
+
+    double S2 = 0.0, S3 = 0.0, S4 = 0.0, S5 = 0.0, nmax = 0.0;
+    double *Dbuf = lds;
+
+    for (int u = wave; u < U; u += W) {
+        double x[D];
+        if (u < D) {
+            // orbits 2 and 3 along axis i, and its fourth difference
+            const int i = u;
+            double f[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double lam = q < 2 ? R.lam2 : R.lam3;
+                const double sg = (q & 1) ? -1.0 : 1.0;
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+                    x[k] = fma(k == i ? sg : 0.0, lam * h[k], c[k]);
+                f[q] = integrand<FAM, D>(x, P);
+            }
+            const double P2 = f[0] + f[1], P3 = f[2] + f[3];
+            S2 += P2;
+            S3 += P3;
+            Dbuf[i * 64 + lane] = fabs((P2 - 2.0 * fc) - (P3 - 2.0 * fc) / 7.0);
+            const double nm = (fabs(f[0]) + fabs(f[1])) +
+                              (fabs(f[2]) + fabs(f[3])) / 7.0 +
+                              (12.0 / 7.0) * fabs(fc);
+            nmax = fmax(nmax, nm);
+        } else if (u < D + NPAIR) {
+            // orbit 4: pair (i, j) with i < j, pairs in row order
+            int i = 0, rem = u - D;
+            while (rem >= D - 1 - i) { rem -= D - 1 - i; ++i; }
+            const int j = i + 1 + rem;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double si = (q & 2) ? -1.0 : 1.0;
+                const double sj = (q & 1) ? -1.0 : 1.0;
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+                    x[k] = fma(k == i ? si : (k == j ? sj : 0.0), l4[k], c[k]);
+                S4 += integrand<FAM, D>(x, P);
+            }
+        } else {
+            // orbit 5: sign vectors 4m..4m+3, bit k set = minus on axis k
+            const int m = u - D - NPAIR;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int b = 4 * m + q;
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+                    x[k] = fma(((b >> k) & 1) ? -1.0 : 1.0, l5[k], c[k]);
+                S5 += integrand<FAM, D>(x, P);
+            }
+        }
+    }
+
+    if (W > 1) {
+        double *part = lds + D * 64;
+        part[(wave * 5 + 0) * 64 + lane] = S2;
+        part[(wave * 5 + 1) * 64 + lane] = S3;
+        part[(wave * 5 + 2) * 64 + lane] = S4;
+        part[(wave * 5 + 3) * 64 + lane] = S5;
+        part[(wave * 5 + 4) * 64 + lane] = nmax;
+        __syncthreads();
+        if (wave == 0) {
+            for (int q = 1; q < W; ++q) {
+                S2 += part[(q * 5 + 0) * 64 + lane];
+                S3 += part[(q * 5 + 1) * 64 + lane];
+                S4 += part[(q * 5 + 2) * 64 + lane];
+                S5 += part[(q * 5 + 3) * 64 + lane];
+                nmax = fmax(nmax, part[(q * 5 + 4) * 64 + lane]);
+            }
+        }
+    } else {
+        __syncthreads();
+    }
+
+    if (wave == 0 && r0 < n) {
+        double vol = 1.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) vol *= 2.0 * h[k];
+        const double s7 = R.w7[0] * fc + R.w7[1] * S2 + R.w7[2] * S3 +
+                          R.w7[3] * S4 + R.w7[4] * S5;
+        const double sn = R.wn[0] * fc + R.wn[1] * S2 + R.wn[2] * S3 +
+                          R.wn[3] * S4 + R.wn[4] * S5;
+        V[r0] = vol * s7;
+        E[r0] = fabs(vol * sn);
+        double dk[D], dmax = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            dk[k] = Dbuf[k * 64 + lane];
+            dmax = fmax(dmax, dk[k]);
+        }
+        const double thr = dmax - 1e-10 * dmax - 1e-12 * nmax;
+        int best = 0;
+        double bw = -1.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            if (dk[k] >= thr && h[k] > bw) { best = k; bw = h[k]; }
+        }
+        K[r0] = (uint8_t)best;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic block reductions (fixed shuffle tree, then waves in order)
+// ---------------------------------------------------------------------------
+struct Acc {
+    double v, e, av, ae, mn, mx;
+    uint32_t cnt;
+    __device__ void init() {
+        v = e = av = ae = 0.0;
+        mn = __builtin_huge_val();
+        mx = -__builtin_huge_val();
+        cnt = 0;
+    }
+    __device__ void add(double V, double E, int a) {
+        v += V;
+        e += E;
+        if (a) { av += V; ae += E; ++cnt; }
+        mn = fmin(mn, E);
+        mx = fmax(mx, E);
+    }
+    __device__ void merge(const Acc &o) {
+        v += o.v; e += o.e; av += o.av; ae += o.ae;
+        mn = fmin(mn, o.mn); mx = fmax(mx, o.mx);
+        cnt += o.cnt;
+    }
+    __device__ void shfl_merge(int off) {
+        Acc o;
+        o.v = __shfl_xor(v, off);
+        o.e = __shfl_xor(e, off);
+        o.av = __shfl_xor(av, off);
+        o.ae = __shfl_xor(ae, off);
+        o.mn = __shfl_xor(mn, off);
+        o.mx = __shfl_xor(mx, off);
+        o.cnt = __shfl_xor(cnt, off);
+        merge(o);
+    }
+};
+
+// Reduces `a` over the block (LIST_THREADS threads); thread 0 writes slot s.
+__device__ void block_reduce_store(Acc a, SegPartials part, int64_t s) {
+    __shared__ Acc wacc[LIST_THREADS / 64];
+    for (int off = 32; off >= 1; off >>= 1) a.shfl_merge(off);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) wacc[wave] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Acc t = wacc[0];
+        for (int q = 1; q < LIST_THREADS / 64; ++q) t.merge(wacc[q]);
+        part.v[s] = t.v;
+        part.e[s] = t.e;
+        part.av[s] = t.av;
+        part.ae[s] = t.ae;
+        part.emin[s] = t.mn;
+        part.emax[s] = t.mx;
+        part.cnt[s] = t.cnt;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// TWO-LEVEL-ERROR + REL-ERR-CLASSIFY + per-segment sums
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(LIST_THREADS)
+k_classify(int64_t n, int paired, const double *__restrict__ V,
+           double *__restrict__ E, const double *__restrict__ Vp, double tau,
+           int relerr, uint8_t *__restrict__ A, SegPartials part) {
+    const int64_t b = blockIdx.x;
+    Acc lo_acc, hi_acc;
+    lo_acc.init();
+    hi_acc.init();
+    if (!paired) {
+        const int64_t s0 = b * SEG, s1 = s0 + SEG < n ? s0 + SEG : n;
+        for (int64_t i = s0 + threadIdx.x; i < s1; i += LIST_THREADS) {
+            const double v = V[i], e = E[i];
+            const int a = relerr ? (e > tau * fabs(v)) : 1;
+            A[i] = (uint8_t)a;
+            lo_acc.add(v, e, a);
+        }
+        block_reduce_store(lo_acc, part, b);
+        return;
+    }
+    const int64_t half = n / 2;
+    const int64_t nh = (half + SEG - 1) / SEG;
+    const int64_t q0 = b * SEG, q1 = q0 + SEG < half ? q0 + SEG : half;
+    for (int64_t q = q0 + threadIdx.x; q < q1; q += LIST_THREADS) {
+        const int64_t ia = q, ib = q + half;
+        const double va = V[ia], vb = V[ib];
+        double ea = E[ia], eb = E[ib];
+        const double delta = fabs(va + vb - Vp[q]) / 4.0;
+        const double S = ea + eb;
+        if (S > 0.0) {
+            const double g = 1.0 + 2.0 * delta / S;
+            ea = ea * g + delta;
+            eb = eb * g + delta;
+        } else {
+            ea = ea + delta;
+            eb = eb + delta;
+        }
+        E[ia] = ea;
+        E[ib] = eb;
+        const int aa = relerr ? (ea > tau * fabs(va)) : 1;
+        const int ab = relerr ? (eb > tau * fabs(vb)) : 1;
+        A[ia] = (uint8_t)aa;
+        A[ib] = (uint8_t)ab;
+        lo_acc.add(va, ea, aa);
+        hi_acc.add(vb, eb, ab);
+    }
+    block_reduce_store(lo_acc, part, b);
+    block_reduce_store(hi_acc, part, nh + b);
+}
+
+// Per-segment count and sums of A = A_rel AND (E > t); E == nullptr: A_rel.
+__global__ void __launch_bounds__(LIST_THREADS)
+k_seg_count(int64_t n, int paired, double t, const double *__restrict__ V,
+            const double *__restrict__ E, const uint8_t *__restrict__ A_rel,
+            SegPartials part) {
+    int64_t s0, s1;
+    seg_range(blockIdx.x, n, paired, &s0, &s1);
+    Acc acc;
+    acc.init();
+    for (int64_t i = s0 + threadIdx.x; i < s1; i += LIST_THREADS) {
+        const double v = V[i], e = E ? E[i] : 0.0;
+        acc.add(v, e, A_rel[i] && (!E || e > t));
+    }
+    block_reduce_store(acc, part, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Single-block totals of the segment partials + exclusive scan of the counts
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(SCAN_THREADS)
+k_reduce_scan(int64_t nseg, SegPartials part, uint32_t *__restrict__ offsets,
+              Totals *__restrict__ tot) {
+    __shared__ uint64_t wsum[SCAN_THREADS / 64];
+    __shared__ Acc wacc[SCAN_THREADS / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t per = (nseg + SCAN_THREADS - 1) / SCAN_THREADS;
+    const int64_t s0 = tid * per, s1 = s0 + per < nseg ? s0 + per : nseg;
+    Acc a;
+    a.init();
+    uint64_t local = 0;
+    for (int64_t s = s0; s < s1; ++s) {
+        a.v += part.v[s];
+        a.e += part.e[s];
+        a.av += part.av[s];
+        a.ae += part.ae[s];
+        a.mn = fmin(a.mn, part.emin[s]);
+        a.mx = fmax(a.mx, part.emax[s]);
+        local += part.cnt[s];
+    }
+    // exclusive scan of `local` over the block
+    uint64_t incl = local;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint64_t y = __shfl_up(incl, off);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    uint64_t wbase = 0;
+    for (int q = 0; q < wave; ++q) wbase += wsum[q];
+    uint64_t run = wbase + incl - local;
+    for (int64_t s = s0; s < s1; ++s) {
+        offsets[s] = (uint32_t)run;
+        run += part.cnt[s];
+    }
+    // totals
+    a.cnt = 0;
+    for (int off = 32; off >= 1; off >>= 1) a.shfl_merge(off);
+    if (lane == 0) wacc[wave] = a;
+    __syncthreads();
+    if (tid == 0) {
+        Acc t = wacc[0];
+        for (int q = 1; q < SCAN_THREADS / 64; ++q) t.merge(wacc[q]);
+        uint64_t total = 0;
+        for (int q = 0; q < SCAN_THREADS / 64; ++q) total += wsum[q];
+        tot->v = t.v;
+        tot->e = t.e;
+        tot->av = t.av;
+        tot->ae = t.ae;
+        tot->emin = t.mn;
+        tot->emax = t.mx;
+        tot->cnt = (double)total;
+        tot->pad = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// THRESHOLD trials: for TRIAL_M candidate thresholds at once, the number of
+// regions that stay active (A_rel AND E > t) and the sum of their errors.
+// ---------------------------------------------------------------------------
+struct Thr {
+    double t[TRIAL_M];
+};
+
+__global__ void __launch_bounds__(LIST_THREADS)
+k_trials(int64_t n, const double *__restrict__ E,
+         const uint8_t *__restrict__ A_rel, const Thr T,
+         double *__restrict__ blk_cnt, double *__restrict__ blk_ae) {
+    uint32_t cnt[TRIAL_M];
+    double ae[TRIAL_M];
+#pragma unroll
+    for (int m = 0; m < TRIAL_M; ++m) { cnt[m] = 0; ae[m] = 0.0; }
+    const int64_t stride = (int64_t)gridDim.x * LIST_THREADS;
+    for (int64_t i = (int64_t)blockIdx.x * LIST_THREADS + threadIdx.x; i < n;
+         i += stride) {
+        const double e = E[i];
+        const bool a = A_rel[i] != 0;
+#pragma unroll
+        for (int m = 0; m < TRIAL_M; ++m) {
+            const bool act = a && e > T.t[m];
+            cnt[m] += act ? 1u : 0u;
+            ae[m] += act ? e : 0.0;
+        }
+    }
+    __shared__ double wred[2][LIST_THREADS / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int m = 0; m < TRIAL_M; ++m) {
+        double c = (double)cnt[m], s = ae[m];
+        for (int off = 32; off >= 1; off >>= 1) {
+            c += __shfl_xor(c, off);
+            s += __shfl_xor(s, off);
+        }
+        __syncthreads();
+        if (lane == 0) { wred[0][wave] = c; wred[1][wave] = s; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double tc = 0.0, ts = 0.0;
+            for (int q = 0; q < LIST_THREADS / 64; ++q) {
+                tc += wred[0][q];
+                ts += wred[1][q];
+            }
+            blk_cnt[(int64_t)m * gridDim.x + blockIdx.x] = tc;
+            blk_ae[(int64_t)m * gridDim.x + blockIdx.x] = ts;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS)
+k_trial_reduce(int nblk, const double *__restrict__ blk_cnt,
+               const double *__restrict__ blk_ae, TrialTotals *__restrict__ tot) {
+    // one wave per candidate, blocks summed in a fixed tree
+    const int lane = threadIdx.x & 63, m = threadIdx.x >> 6;
+    if (m >= TRIAL_M) return;
+    double c = 0.0, s = 0.0;
+    for (int b = lane; b < nblk; b += 64) {
+        c += blk_cnt[(int64_t)m * nblk + b];
+        s += blk_ae[(int64_t)m * nblk + b];
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        c += __shfl_xor(c, off);
+        s += __shfl_xor(s, off);
+    }
+    if (lane == 0) {
+        tot->cnt[m] = c;
+        tot->ae[m] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FILTER + parent update + SPLIT: stable compaction by ballot prefix within
+// each segment, segment bases from the exclusive scan.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(LIST_THREADS)
+k_compact_split(int d, int64_t n, int paired, double t,
+                const uint8_t *__restrict__ A_rel, const double *__restrict__ E,
+                const double *__restrict__ V, const uint8_t *__restrict__ K,
+                const double *__restrict__ lo, const double *__restrict__ w,
+                int64_t ld_in, const uint32_t *__restrict__ offsets,
+                int64_t na, double *__restrict__ lo_out,
+                double *__restrict__ w_out, int64_t ld_out,
+                double *__restrict__ Vp) {
+    __shared__ uint32_t wtot[LIST_THREADS / 64];
+    int64_t s0, s1;
+    seg_range(blockIdx.x, n, paired, &s0, &s1);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int64_t base = offsets[blockIdx.x];
+    for (int64_t i0 = s0; i0 < s1; i0 += LIST_THREADS) {
+        const int64_t i = i0 + threadIdx.x;
+        const bool act = i < s1 && A_rel[i] && (!E || E[i] > t);
+        const uint64_t mask = __ballot(act);
+        const uint32_t pre = __popcll(mask & ((1ull << lane) - 1ull));
+        if (lane == 0) wtot[wave] = __popcll(mask);
+        __syncthreads();
+        uint32_t wpre = 0, total = 0;
+        for (int q = 0; q < LIST_THREADS / 64; ++q) {
+            if (q < wave) wpre += wtot[q];
+            total += wtot[q];
+        }
+        if (act) {
+            const int64_t j = base + wpre + pre;
+            const int ax = K[i];
+            for (int k = 0; k < d; ++k) {
+                const double l = lo[k * ld_in + i], ww = w[k * ld_in + i];
+                if (k == ax) {
+                    const double half = ww * 0.5;
+                    lo_out[k * ld_out + j] = l;
+                    w_out[k * ld_out + j] = half;
+                    lo_out[k * ld_out + j + na] = l + half;
+                    w_out[k * ld_out + j + na] = half;
+                } else {
+                    lo_out[k * ld_out + j] = l;
+                    w_out[k * ld_out + j] = ww;
+                    lo_out[k * ld_out + j + na] = l;
+                    w_out[k * ld_out + j + na] = ww;
+                }
+            }
+            Vp[j] = V[i];
+        }
+        base += total;
+        __syncthreads();
+    }
+}
+
+__global__ void k_apply_threshold(int64_t n, double t,
+                                  const uint8_t *__restrict__ A_rel,
+                                  const double *__restrict__ E,
+                                  uint8_t *__restrict__ A_out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) A_out[i] = (uint8_t)(A_rel[i] && E[i] > t);
+}
+
+// ---------------------------------------------------------------------------
+// UNIFORM-SPLIT: g^d boxes, axis 0 varying fastest. Corners are a_k plus
+// digit * width_k rounded twice, exactly as written (no contraction).
+// ---------------------------------------------------------------------------
+struct Box {
+    double a[PG_DIM_MAX], width[PG_DIM_MAX];
+};
+
+__global__ void k_init(int d, int g, int64_t n, const Box B,
+                       double *__restrict__ lo, double *__restrict__ w,
+                       int64_t ld) {
+#pragma clang fp contract(off)
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    int64_t q = r;
+    for (int k = 0; k < d; ++k) {
+        const int64_t digit = q % g;
+        q /= g;
+        const double off = (double)digit * B.width[k];
+        lo[k * ld + r] = B.a[k] + off;
+        w[k * ld + r] = B.width[k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+typedef void (*EvalKernel)(const FParams, const Rule, int64_t, const double *,
+                           const double *, int64_t, double *, double *,
+                           uint8_t *);
+
+template <int FAM>
+static EvalKernel eval_table(int d) {
+    switch (d) {
+    case 2: return k_evaluate<FAM, 2>;
+    case 3: return k_evaluate<FAM, 3>;
+    case 4: return k_evaluate<FAM, 4>;
+    case 5: return k_evaluate<FAM, 5>;
+    case 6: return k_evaluate<FAM, 6>;
+    case 7: return k_evaluate<FAM, 7>;
+    case 8: return k_evaluate<FAM, 8>;
+    case 9: return k_evaluate<FAM, 9>;
+    case 10: return k_evaluate<FAM, 10>;
+    default: return nullptr;
+    }
+}
+
+static EvalKernel eval_kernel(int family, int d) {
+    switch (family) {
+    case PG_PRODUCT_PEAK: return eval_table<PG_PRODUCT_PEAK>(d);
+    case PG_GAUSSIAN: return eval_table<PG_GAUSSIAN>(d);
+    case PG_OSCILLATORY: return eval_table<PG_OSCILLATORY>(d);
+    case PG_CORNER_PEAK: return eval_table<PG_CORNER_PEAK>(d);
+    case PG_MONOMIAL: return eval_table<PG_MONOMIAL>(d);
+    default: return nullptr;
+    }
+}
+
+bool evaluate_supported(int family, int d) {
+    return eval_kernel(family, d) != nullptr;
+}
+
+int evaluate_max_waves(int d) {
+    const int units = d + d * (d - 1) / 2 + (1 << d) / 4;
+    int w = 1;
+    while (w * 2 <= EVAL_MAX_WAVES && w * 2 <= units) w *= 2;
+    return w;
+}
+
+hipError_t launch_evaluate(hipStream_t st, int family, int d,
+                           const FParams &P, const Rule &R, int64_t n,
+                           const double *lo, const double *w, int64_t ld,
+                           double *V, double *E, uint8_t *K, int waves) {
+    EvalKernel k = eval_kernel(family, d);
+    if (!k) return hipErrorInvalidValue;
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 63) / 64;
+    const size_t lds = sizeof(double) * 64 * (size_t)(d + (waves > 1 ? 5 * waves : 0));
+    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * waves), lds, st, P,
+                       R, n, lo, w, ld, V, E, K);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(hipStream_t st, int d, int g, const double *a,
+                       const double *width, double *lo, double *w,
+                       int64_t ld) {
+    Box B;
+    int64_t n = 1;
+    for (int k = 0; k < d; ++k) {
+        B.a[k] = a[k];
+        B.width[k] = width[k];
+        n *= g;
+    }
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_init, dim3((unsigned)blocks), dim3(256), 0, st, d, g,
+                       n, B, lo, w, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_classify(hipStream_t st, int64_t n, int paired,
+                           const double *V, double *E, const double *Vp,
+                           double tau, int relerr, uint8_t *A,
+                           SegPartials part) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = paired ? seg_count(n, 1) / 2 : seg_count(n, 0);
+    hipLaunchKernelGGL(k_classify, dim3((unsigned)blocks), dim3(LIST_THREADS),
+                       0, st, n, paired, V, E, Vp, tau, relerr, A, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_count(hipStream_t st, int64_t n, int paired, double t,
+                            const double *V, const double *E,
+                            const uint8_t *A_rel, SegPartials part) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_seg_count, dim3((unsigned)seg_count(n, paired)),
+                       dim3(LIST_THREADS), 0, st, n, paired, t, V, E, A_rel,
+                       part);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_scan(hipStream_t st, int64_t nseg, SegPartials part,
+                              uint32_t *offsets, Totals *tot) {
+    hipLaunchKernelGGL(k_reduce_scan, dim3(1), dim3(SCAN_THREADS), 0, st, nseg,
+                       part, offsets, tot);
+    return hipGetLastError();
+}
+
+hipError_t launch_trials(hipStream_t st, int64_t n, const double *E,
+                         const uint8_t *A_rel, const double *thr,
+                         double *blk_cnt, double *blk_ae, TrialTotals *tot) {
+    Thr T;
+    for (int m = 0; m < TRIAL_M; ++m) T.t[m] = thr[m];
+    int64_t blocks = (n + LIST_THREADS - 1) / LIST_THREADS;
+    if (blocks > TRIAL_BLOCKS) blocks = TRIAL_BLOCKS;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_trials, dim3((unsigned)blocks), dim3(LIST_THREADS), 0,
+                       st, n, E, A_rel, T, blk_cnt, blk_ae);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_trial_reduce, dim3(1), dim3(SCAN_THREADS), 0, st,
+                       (int)blocks, blk_cnt, blk_ae, tot);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_split(hipStream_t st, int d, int64_t n, int paired,
+                                double t, const uint8_t *A_rel,
+                                const double *E, const double *V,
+                                const uint8_t *K, const double *lo,
+                                const double *w, int64_t ld_in,
+                                const uint32_t *offsets, int64_t n_active,
+                                double *lo_out, double *w_out, int64_t ld_out,
+                                double *Vp) {
+    if (n <= 0 || n_active <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_compact_split, dim3((unsigned)seg_count(n, paired)),
+                       dim3(LIST_THREADS), 0, st, d, n, paired, t, A_rel, E, V,
+                       K, lo, w, ld_in, offsets, n_active, lo_out, w_out,
+                       ld_out, Vp);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_threshold(hipStream_t st, int64_t n, double t,
+                                  const uint8_t *A_rel, const double *E,
+                                  uint8_t *A_out) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_apply_threshold, dim3((unsigned)((n + 255) / 256)),
+                       dim3(256), 0, st, n, t, A_rel, E, A_out);
+    return hipGetLastError();
+}
+
+}  // namespace pg

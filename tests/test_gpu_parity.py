@@ -1,0 +1,325 @@
+"""GPU parity: the HIP library (through the C-ABI) against the CPU oracle.
+
+Each test prints the case it runs before touching the GPU.
+"""
+import os
+import sys
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from workloads import closed_forms as cf
+
+from parity import assert_region_parity, rel_close
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2104_06494_amd as pg
+    torch.cuda.set_device(0)
+    c = pg.Context(capacity=1 << 21, dim_max=10)
+    yield c
+    c.close()
+
+
+def _dev(x, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+def _params(family, d, seed):
+    if family == "product_peak":
+        return W.product_peak_params(d, seed)
+    if family == "gaussian":
+        return W.gaussian_params(d, seed)
+    if family == "oscillatory":
+        return W.oscillatory_params(d, seed)
+    return W.corner_peak_params(d, seed)
+
+
+# ---------------------------------------------------------------------------
+# EVALUATE
+# ---------------------------------------------------------------------------
+
+CASES = [(fam, d, n) for fam in ("product_peak", "gaussian", "oscillatory", "corner_peak")
+         for d, n in ((2, 1), (3, 65), (5, 1000), (6, 3001), (8, 777))]
+
+
+@pytest.mark.parametrize("family,d,n", CASES)
+def test_evaluate_parity(ctx, family, d, n):
+    _say("evaluate", family, d, n)
+    p = _params(family, d, seed=10 + d)
+    lo, w = W.random_boxes(d, n, seed=100 + d + n)
+    V, E, K = ctx.evaluate(family, p, _dev(lo), _dev(w))
+    torch.cuda.synchronize()
+    ref = oracle.eval_regions(family, d, p, lo, w)
+    assert_region_parity(ref, lo, w, V.cpu().numpy(), E.cpu().numpy(), K.cpu().numpy())
+
+
+@pytest.mark.parametrize("family,d,n", [("gaussian", 5, 200_000), ("oscillatory", 8, 140_000),
+                                        ("product_peak", 3, 200_000),
+                                        ("corner_peak", 6, 140_000)])
+def test_evaluate_parity_one_wave_per_block(ctx, family, d, n):
+    """Lists long enough that each block runs a single wave."""
+    _say("evaluate-large", family, d, n)
+    p = _params(family, d, seed=3)
+    lo, w = W.random_boxes(d, n, seed=7, dyadic_bits=12)
+    V, E, K = ctx.evaluate(family, p, _dev(lo), _dev(w))
+    torch.cuda.synchronize()
+    ref = oracle.eval_regions(family, d, p, lo, w)
+    assert_region_parity(ref, lo, w, V.cpu().numpy(), E.cpu().numpy(), K.cpu().numpy())
+
+
+def test_evaluate_strided_rows(ctx):
+    """Rows of lo/w taken from a wider buffer (leading dimension > n)."""
+    d, n, ld = 4, 300, 512
+    _say("evaluate-strided", d, n, ld)
+    p = _params("gaussian", d, seed=1)
+    lo, w = W.random_boxes(d, n, seed=2)
+    blo = torch.zeros(d, ld, dtype=torch.float64, device="cuda")
+    bw = torch.zeros_like(blo)
+    blo[:, :n] = _dev(lo)
+    bw[:, :n] = _dev(w)
+    V, E, K = ctx.evaluate("gaussian", p, blo[:, :n], bw[:, :n])
+    ref = oracle.eval_regions("gaussian", d, p, lo, w)
+    assert_region_parity(ref, lo, w, V.cpu().numpy(), E.cpu().numpy(), K.cpu().numpy())
+
+
+@pytest.mark.parametrize("d", [2, 3, 5, 8])
+def test_evaluate_exact_on_monomials(ctx, d):
+    """Independent of the oracle: the degree-7 rule is exact on monomials of
+    degree <= 7 and its null rule vanishes up to degree 5 (exact rationals)."""
+    _say("monomial-exactness", d)
+    from itertools import combinations_with_replacement
+    lo = np.array([[-0.5], [0.25], [0.0], [-1.0], [0.5], [0.125], [-0.25], [0.0]])[:d]
+    w = np.array([[1.0], [0.5], [0.25], [2.0], [0.5], [1.0], [0.75], [0.5]])[:d]
+    for deg in (0, 1, 3, 5, 6, 7):
+        for combo in combinations_with_replacement(range(d), deg):
+            alpha = [0] * d
+            for i in combo:
+                alpha[i] += 1
+            V, E, K = ctx.evaluate("monomial", np.array(alpha, float), _dev(lo), _dev(w))
+            v, e = float(V[0]), float(E[0])
+            exact = cf.monomial(alpha, lo[:, 0], lo[:, 0] + w[:, 0])
+            scale = float(cf.monomial([2 * a for a in alpha], lo[:, 0] - 1e-300,
+                                      lo[:, 0] + w[:, 0])) ** 0.5 + 1e-30
+            assert abs(Fraction(v) - exact) <= Fraction(1e-13) * Fraction(scale) * 50, (alpha, v, float(exact))
+            if deg <= 5:
+                assert e <= 1e-13 * scale * 50, (alpha, e)
+
+
+def test_evaluate_empty_and_invalid(ctx):
+    _say("evaluate-edge")
+    import paper_2104_06494_amd as pg
+    z = torch.zeros(3, 0, dtype=torch.float64, device="cuda")
+    V, E, K = ctx.evaluate("gaussian", _params("gaussian", 3, 1), z, z)
+    assert V.numel() == 0
+    with pytest.raises(pg.PaganiError):
+        ctx.evaluate("gaussian", np.ones(5), _dev(np.zeros((3, 4))), _dev(np.ones((3, 4))))
+    with pytest.raises(pg.PaganiError):
+        ctx.integrate("gaussian", 11, np.ones(22))
+
+
+# ---------------------------------------------------------------------------
+# TWO-LEVEL + CLASSIFY, THRESHOLD, FILTER + SPLIT
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,paired", [(1, 0), (4097, 0), (2, 1), (2 * 5003, 1),
+                                      (2 * 70000, 1)])
+def test_classify_parity(ctx, n, paired):
+    _say("classify", n, paired)
+    rng = np.random.default_rng(n)
+    V = rng.lognormal(size=n) * 1e-5
+    E = V * 10.0 ** rng.uniform(-9, -3, size=n)
+    E[::17] = 0.0
+    tau = 1e-6
+    Vp = None
+    if paired:
+        m = n // 2
+        Vp = V[:m] + V[m:] + rng.normal(scale=1e-9, size=m)
+    Vd, Ed = _dev(V), _dev(E)
+    A, sums = ctx.classify(Vd, Ed, _dev(Vp) if paired else None, paired=bool(paired),
+                           rel_tol=tau)
+    E_ref = oracle.two_level(V, E, Vp) if paired else E
+    A_ref = oracle.classify(V, E_ref, tau)
+    np.testing.assert_allclose(Ed.cpu().numpy(), E_ref, rtol=4e-16, atol=0)
+    np.testing.assert_array_equal(A.cpu().numpy(), A_ref)
+    ref = [oracle.csum(V), oracle.csum(E_ref), oracle.csum(V, A_ref),
+           oracle.csum(E_ref, A_ref), float(A_ref.sum()), E_ref.min(), E_ref.max()]
+    for k in range(4):
+        assert rel_close(sums[k], ref[k], 1e-13), (k, sums[k], ref[k])
+    assert sums[4:] == ref[4:]
+
+
+@pytest.mark.parametrize("seed,mem", [(0, 0), (1, 1), (2, 0), (3, 1), (4, 0)])
+def test_threshold_search_parity(ctx, seed, mem):
+    _say("threshold", seed, mem)
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1000, 60000))
+    E = rng.lognormal(sigma=2.5, size=n) * 1e-9
+    A_rel = (rng.uniform(size=n) < 0.9).astype(np.uint8)
+    v = 1.8e-5
+    tau = float(10.0 ** rng.uniform(-7, -4))
+    e_it = oracle.csum(E)
+    e_f = float(rng.uniform(0, 0.3)) * tau * v
+    ok, A, t, trials = ctx.threshold_search(_dev(E), _dev(A_rel, torch.uint8), v,
+                                            e_it + e_f, e_it, tau, mem)
+    rok, rA, rt, rtrials, _ = oracle.threshold_search(E, A_rel, v, e_it + e_f, e_it,
+                                                      tau, mem)
+    assert (ok, trials) == (rok, rtrials)
+    if ok:
+        assert rel_close(t, rt, 1e-12)
+        diff = np.flatnonzero(A.cpu().numpy() != rA)
+        assert all(abs(E[i] - rt) <= 1e-12 * rt for i in diff)
+    else:
+        np.testing.assert_array_equal(A.cpu().numpy(), A_rel)
+
+
+@pytest.mark.parametrize("d,n", [(2, 1), (3, 2049), (5, 4096), (8, 10001)])
+def test_filter_split_bit_exact(ctx, d, n):
+    _say("filter-split", d, n)
+    rng = np.random.default_rng(d * n)
+    lo, w = W.random_boxes(d, n, seed=n, dyadic_bits=20)
+    K = rng.integers(0, d, size=n).astype(np.uint8)
+    V = rng.normal(size=n)
+    A = (rng.uniform(size=n) < 0.55).astype(np.uint8)
+    lo2, w2, Vp = ctx.filter_split(_dev(lo), _dev(w), _dev(K, torch.uint8), _dev(V),
+                                   _dev(A, torch.uint8))
+    rlo, rw, rVp = oracle.filter_split(d, lo, w, K, V, A)
+    np.testing.assert_array_equal(lo2.cpu().numpy(), rlo)
+    np.testing.assert_array_equal(w2.cpu().numpy(), rw)
+    np.testing.assert_array_equal(Vp.cpu().numpy(), rVp)
+
+
+def test_filter_split_none_active(ctx):
+    _say("filter-split-empty")
+    d, n = 3, 100
+    lo, w = W.random_boxes(d, n, seed=1)
+    z = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    lo2, w2, Vp = ctx.filter_split(_dev(lo), _dev(w), z, _dev(np.ones(n)), z)
+    assert lo2.shape == (d, 0) and Vp.numel() == 0
+
+
+# ---------------------------------------------------------------------------
+# Whole runs: oracle replays the GPU's decision trace
+# ---------------------------------------------------------------------------
+
+def _replay(ctx, wl, tmp_path, **kw):
+    trace = str(tmp_path / "trace.bin")
+    r = ctx.integrate_workload(wl, trace_path=trace, **kw)
+    o = oracle.integrate_workload(wl, replay_path=trace, **kw)
+    return r, o
+
+
+def _assert_replay(r, o, rel=1e-10):
+    rep = o.replay
+    hard = {k: v for k, v in rep.items() if k.endswith("_hard") and v}
+    assert not hard, (hard, rep)
+    assert r.status == o.status and r.iterations == o.iterations
+    assert r.regions_evaluated == o.regions_evaluated
+    assert rel_close(r.estimate, o.estimate, rel), (r.estimate, o.estimate)
+    assert rel_close(r.error, o.error, rel), (r.error, o.error)
+
+
+REPLAY = [
+    ("product_peak_d3", lambda: W.product_peak_d3(), {}),
+    ("product_peak_d3_1e-6", lambda: W.product_peak_d3(), dict(rel_tol=1e-6)),
+    ("gaussian_d5_1e-4", lambda: W.gaussian_d5(), dict(rel_tol=1e-4)),
+    ("oscillatory_d8_relerr_off", lambda: W.oscillatory_d8(0), {}),
+    ("oscillatory_d8_relerr_on", lambda: W.oscillatory_d8(1), {}),
+    ("gaussian_d5_max_iters", lambda: W.gaussian_d5(), dict(max_iters=3)),
+    ("gaussian_d5_memory", lambda: W.gaussian_d5(), dict(max_regions=3000,
+                                                         threshold_filter=0)),
+]
+
+
+@pytest.mark.parametrize("name,mk,kw", REPLAY, ids=[c[0] for c in REPLAY])
+def test_integrate_replay(ctx, tmp_path, name, mk, kw):
+    _say("replay", name)
+    wl = mk()
+    r, o = _replay(ctx, wl, tmp_path, **kw)
+    _assert_replay(r, o)
+    if r.status_name == "OK":
+        exact = cf.exact(wl.family, wl.params, wl.d)
+        tau = kw.get("rel_tol", wl.rel_tol)
+        assert abs(r.estimate - exact) <= tau * abs(exact)
+        assert r.error <= tau * abs(r.estimate)
+
+
+def test_headline_workload_replay(ctx, tmp_path):
+    """d=5 Gaussian to 1e-6 with the 2^21-region cap: replay parity, the
+    closed form met, the memory trigger fired (the list reached the cap)."""
+    _say("replay-headline")
+    wl = W.gaussian_d5()
+    r, o = _replay(ctx, wl, tmp_path)
+    _assert_replay(r, o)
+    exact = cf.exact(wl.family, wl.params, wl.d)
+    assert r.status_name == "OK"
+    assert abs(r.estimate - exact) <= wl.rel_tol * abs(exact)
+    assert r.peak_regions == wl.max_regions
+
+
+def test_headline_sampled_regions(ctx):
+    """Full-size run as the benchmark times it; then the live list of its last
+    iteration is sampled and every sampled region is evaluated by the oracle
+    (V and K come from the run itself; E is re-evaluated raw on the whole
+    list, which is as long as the run's largest launches)."""
+    _say("headline-sampled")
+    wl = W.gaussian_d5()
+    r = ctx.integrate_workload(wl)
+    L = ctx.last_regions()
+    n = L["n"]
+    assert n > 100_000
+    rng = np.random.default_rng(0)
+    idx = np.sort(rng.choice(n, size=3000, replace=False))
+    lo = L["lo"].cpu().numpy()
+    w = L["w"].cpu().numpy()
+    V = L["V"].cpu().numpy()
+    K = L["K"].cpu().numpy()
+    lo_full, w_full = L["lo"].contiguous(), L["w"].contiguous()
+    V2, E2, K2 = ctx.evaluate(wl.family, wl.params, lo_full, w_full)
+    ref = oracle.eval_regions(wl.family, wl.d, wl.params, lo[:, idx], w[:, idx])
+    assert_region_parity(ref, lo[:, idx], w[:, idx], V[idx], E2.cpu().numpy()[idx],
+                         K[idx])
+    np.testing.assert_array_equal(V2.cpu().numpy(), V)       # same kernel, same bits
+    # boxes lie inside the unit cube and their volume does not exceed it
+    assert (lo >= 0).all() and (lo + w <= 1).all()
+    assert np.prod(w, axis=0).sum() <= 1.0
+
+
+def test_runs_are_bitwise_reproducible(ctx):
+    _say("determinism")
+    wl = W.gaussian_d5()
+    r1 = ctx.integrate_workload(wl, rel_tol=1e-5)
+    r2 = ctx.integrate_workload(wl, rel_tol=1e-5)
+    assert (r1.estimate, r1.error, r1.regions_evaluated) == \
+        (r2.estimate, r2.error, r2.regions_evaluated)
+
+
+def test_integrate_invalid_arguments(ctx):
+    _say("integrate-invalid")
+    import paper_2104_06494_amd as pg
+    p = W.gaussian_params(3, 1)
+    with pytest.raises(pg.PaganiError):
+        ctx.integrate("gaussian", 3, p, lo=[0, 0, 1], hi=[1, 1, 1])
+    with pytest.raises(pg.PaganiError):
+        ctx.integrate("gaussian", 3, p, rel_tol=0, abs_tol=0)
+    with pytest.raises(pg.PaganiError):
+        ctx.integrate("gaussian", 3, p, init_splits=200)          # 200^3 > cap
+    with pytest.raises(pg.PaganiError):
+        ctx.integrate("gaussian", 3, p, max_regions=1 << 30)      # above capacity
+    with pytest.raises(pg.PaganiError):
+        ctx.integrate("gaussian", 3, p[:5])                        # wrong params

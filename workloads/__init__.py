@@ -59,7 +59,7 @@ class Workload:
     rel_tol: float
     abs_tol: float = 1e-20
     init_splits: int = 4
-    max_regions: int = 1 << 22
+    max_regions: int = 1 << 21
     max_iters: int = 100
     relerr_filter: int = 1
     threshold_filter: int = 1
