@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Benchmark of the PAGANI hot path on one MI355X.
+
+A step is one whole integration (Algorithm 2 to convergence) of the d=5
+Gaussian exp(-sum a_i^2 (x_i - u_i)^2) on [0,1]^5 (a ~ U[10,25],
+u ~ U[0.3,0.7], seed 2), 4^5 initial grid, rel_tol 1e-6, live list capped at
+2^21 regions. Inputs (the integrand's parameters) are resident before the
+timed region; each step allocates nothing (the workspace is set up once).
+
+Prints one JSON line:
+  value       integrand evaluations per second over the K timed steps
+              (sum of regions evaluated x 93 points / wall time)
+  roofline    the EVALUATE kernel (the method's arithmetic) against MI355X's
+              FP64 vector peak, from HIP events recorded on its stream
+  cpu_baseline  the CPU oracle (single thread) on a bounded sample of the
+              same workload: the first 12 iterations of the same run
+
+Other modes feed the profiles: --mode integrand (integrand values only, to
+count one evaluation's FP64 operations with rocprofv3 counters) and
+--mode copy (a plain device copy of known size, to scale FETCH_SIZE /
+WRITE_SIZE).
+"""
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# FP64 operations of one Gaussian evaluation in 5 dimensions, counted with
+# rocprofv3 ((ADD + MUL + TRANS + 2 FMA)_F64 per evaluation) on the
+# integrand-only kernel; see profiles/evaluate_gaussian_d5_counters.txt.
+# Algorithmic FLOP per region = 93 points x (F + 1 orbit accumulation).
+F_GAUSSIAN_D5 = 47.0
+# HBM bytes per evaluate launch of this workload from FETCH_SIZE / WRITE_SIZE
+# (scaled by a plain copy), valid only for the kernel source they were taken
+# on (first 16 hex digits of its sha256); reported as null otherwise.
+EVAL_TRAFFIC = {"bytes_per_launch": 37555060.0, "kernel_sha256": "7bdd3c4a3d3760c5",
+                "profile": "profiles/evaluate_gaussian_d5_counters.txt"}
+# MI355X FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz.
+PEAK_FP64_TFLOPS = 78.6
+
+
+def _kernel_sha():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2104_06494_amd", "csrc", "pg_kernels.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def headline(args):
+    import torch
+    import paper_2104_06494_amd as pg
+    import workloads as W
+    from workloads import closed_forms as cf
+
+    wl = W.gaussian_d5()
+    npts = wl.npoints
+    torch.cuda.set_device(0)
+    ctx = pg.Context(capacity=wl.max_regions, dim_max=wl.d)
+    for _ in range(args.warmup):
+        ctx.integrate_workload(wl, timing=True)
+    torch.cuda.synchronize()
+    results, step_s = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        r = ctx.integrate_workload(wl, timing=True)
+        step_s.append(time.perf_counter() - ts)
+        results.append(r)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    fevals = sum(r.fevals for r in results)
+    value = fevals / wall
+    r0 = results[0]
+    exact = cf.exact(wl.family, wl.params, wl.d)
+    eval_ms = sum(r.phase_ms[0] for r in results)
+    launches = sum(r.eval_launches for r in results)
+    regions = sum(r.regions_evaluated for r in results)
+    alg_flop = regions * npts * (F_GAUSSIAN_D5 + 1.0)
+    achieved = alg_flop / (eval_ms * 1e-3) / 1e12
+    phases = [sum(r.phase_ms[k] for r in results) / len(results) for k in range(4)]
+    out = {
+        "metric": "FP64 integrand evals/s + time-to-tol at 1e-6; batched & adjoint vs plain, 1 GPU",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "gaussian_d5_tol1e-6", "family": "gaussian", "d": 5,
+                   "rel_tol": wl.rel_tol, "init_grid": "4^5",
+                   "max_regions": wl.max_regions, "points_per_region": npts,
+                   "seed": 2},
+        "time_to_tol_ms": 1e3 * statistics.median(step_s),
+        "result": {"status": r0.status_name, "estimate": r0.estimate,
+                   "error": r0.error, "true_rel_err": abs(r0.estimate - exact) / abs(exact),
+                   "iterations": r0.iterations, "regions_evaluated": r0.regions_evaluated,
+                   "peak_regions": r0.peak_regions, "fevals": r0.fevals,
+                   "threshold_calls": r0.threshold_calls,
+                   "threshold_trials": r0.threshold_trials},
+        "phase_ms_per_step": {"evaluate": phases[0], "post_process": phases[1],
+                              "threshold": phases[2], "filter_split": phases[3]},
+        "roofline": {
+            "kernel": "k_evaluate<gaussian,5>",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_TFLOPS,
+            "traffic": (EVAL_TRAFFIC["bytes_per_launch"]
+                        if _kernel_sha() == EVAL_TRAFFIC["kernel_sha256"] else None),
+            "traffic_unit": "HBM bytes per launch",
+            "avg_launch_ms": eval_ms / launches,
+            "alg_flop_per_launch": alg_flop / launches,
+            "eval_evals_per_s": regions * npts / (eval_ms * 1e-3),
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(wl):
+    """The CPU oracle, single-threaded, on the first 12 iterations of the same
+    run (about 2e6 regions x 93 points)."""
+    import oracle
+    r = oracle.integrate_workload(wl, max_iters=12)
+    return {"value": r.fevals / r.seconds, "unit": "evals/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"first 12 iterations of the same run: {r.regions_evaluated} "
+                      f"regions, {r.fevals} evaluations, {r.seconds:.1f} s"}
+
+
+def integrand_mode(args):
+    """f alone at 2^22 points, for counting an evaluation's FP64 operations."""
+    import numpy as np
+    import torch
+    import paper_2104_06494_amd as pg
+    import workloads as W
+    torch.cuda.set_device(0)
+    wl = W.gaussian_d5()
+    n = 1 << 22
+    x = torch.rand(wl.d, n, dtype=torch.float64, device="cuda")
+    ctx = pg.Context(capacity=1 << 10, dim_max=wl.d)
+    for _ in range(args.warmup + args.steps):
+        y = ctx.integrand_values(wl.family, wl.params, x)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "integrand", "points": n, "launches": args.warmup + args.steps,
+                      "checksum": float(y.sum())}), flush=True)
+
+
+def copy_mode(args):
+    """A plain device copy of 2^28 bytes, for scaling the HBM byte counters."""
+    import torch
+    torch.cuda.set_device(0)
+    nbytes = 1 << 28
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(args.warmup + args.steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "copy", "bytes_read_per_launch": nbytes,
+                      "bytes_written_per_launch": nbytes,
+                      "launches": args.warmup + args.steps}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__,
+                                 formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--mode", choices=["headline", "integrand", "copy"], default="headline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not "
+              "supported (the method's multi-GPU sharding is a design note, not code)",
+              file=sys.stderr)
+        sys.exit(2)
+    {"headline": headline, "integrand": integrand_mode, "copy": copy_mode}[args.mode](args)
+
+
+if __name__ == "__main__":
+    main()

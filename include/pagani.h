@@ -177,6 +177,15 @@ int pg_evaluate(pg_context *ctx, const pg_integrand *f, int64_t n,
                 double *E, uint8_t *K);
 
 /*
+ * The integrand alone: y[i] = f(x_i) for n points x_i with coordinates
+ * x[k * ld + i] (device arrays). The same inlined code as EVALUATE uses;
+ * for checking an integrand and for counting its cost. Queued on the
+ * context's stream.
+ */
+int pg_integrand_values(pg_context *ctx, const pg_integrand *f, int64_t n,
+                        const double *x, int64_t ld, double *y);
+
+/*
  * TWO-LEVEL-ERROR + REL-ERR-CLASSIFY + the sums of Algorithm 2 on n
  * regions. When `paired` is 1, n is even and regions i and i + n/2 are the
  * halves of the parent whose estimate is Vp[i]; E is then refined in place

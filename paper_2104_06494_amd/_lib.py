@@ -22,7 +22,7 @@ STATUS = {0: "OK", 1: "MAX_ITERS", 2: "MEMORY_EXHAUSTED", 3: "NO_ACTIVE",
 EXPORTS = ["pg_default_options", "pg_workspace_bytes", "pg_context_create",
            "pg_context_destroy", "pg_context_set_stream", "pg_last_error",
            "pg_integrate", "pg_last_regions", "pg_evaluate", "pg_classify",
-           "pg_threshold_search", "pg_filter_split"]
+           "pg_threshold_search", "pg_filter_split", "pg_integrand_values"]
 
 
 class Integrand(C.Structure):
@@ -96,6 +96,8 @@ def load():
     L.pg_evaluate.argtypes = [vp, C.POINTER(Integrand), i64, vp, vp, i64, vp,
                               vp, vp]
     L.pg_evaluate.restype = C.c_int
+    L.pg_integrand_values.argtypes = [vp, C.POINTER(Integrand), i64, vp, i64, vp]
+    L.pg_integrand_values.restype = C.c_int
     L.pg_classify.argtypes = [vp, i64, C.c_int, vp, vp, vp, C.c_double, C.c_int,
                               vp, C.POINTER(C.c_double)]
     L.pg_classify.restype = C.c_int

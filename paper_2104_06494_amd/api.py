@@ -205,6 +205,18 @@ class Context:
             raise self._err(rc)
         return V, E, K
 
+    def integrand_values(self, family, params, x):
+        """f at the points x ([d, n] float64 tensor, unit column stride)."""
+        self._bind_stream()
+        ld = self._soa_ld(x, x)
+        d, n = x.shape
+        y = torch.empty(n, dtype=torch.float64, device=self.device)
+        f, keep = _integrand(family, d, params)
+        rc = self.lib.pg_integrand_values(self.h, C.byref(f), n, _ptr(x), ld, _ptr(y))
+        if rc:
+            raise self._err(rc)
+        return y
+
     def classify(self, V, E, Vp=None, paired=False, rel_tol=1e-3, relerr_filter=1):
         """TWO-LEVEL-ERROR (paired lists, in place on E) + REL-ERR-CLASSIFY.
         Returns (A, sums) with sums = [sum V, sum E, sum AV, sum AE, sum A,

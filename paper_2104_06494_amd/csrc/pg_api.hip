@@ -416,6 +416,21 @@ int pg_evaluate(pg_context *ctx, const pg_integrand *f, int64_t n,
     return PG_OK;
 }
 
+int pg_integrand_values(pg_context *ctx, const pg_integrand *f, int64_t n,
+                        const double *x, int64_t ld, double *y) {
+    if (!ctx) return PG_EINVAL;
+    FParams P;
+    int rc = make_params(ctx, f, &P);
+    if (rc) return rc;
+    if (ld < n || n < 0) return fail(ctx, PG_EINVAL, "bad n / ld");
+    if (n == 0) return PG_OK;
+    if (!x || !y) return fail(ctx, PG_EINVAL, "NULL array");
+    HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+    HIP_OR_FAIL(ctx, launch_fvalues(ctx->stream, f->family, f->dim, P, n, x,
+                                    ld, y));
+    return PG_OK;
+}
+
 int pg_classify(pg_context *ctx, int64_t n, int paired, const double *V,
                 double *E, const double *Vp, double rel_tol,
                 int relerr_filter, uint8_t *A, double *sums) {

@@ -93,6 +93,8 @@ hipError_t launch_evaluate(hipStream_t st, int family, int d,
                            const double *lo, const double *w, int64_t ld,
                            double *V, double *E, uint8_t *K, int waves);
 bool evaluate_supported(int family, int d);
+hipError_t launch_fvalues(hipStream_t st, int family, int d, const FParams &P,
+                          int64_t n, const double *x, int64_t ld, double *y);
 int evaluate_max_waves(int d);
 hipError_t launch_classify(hipStream_t st, int64_t n, int paired,
                            const double *V, double *E, const double *Vp,

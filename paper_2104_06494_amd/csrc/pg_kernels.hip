@@ -82,7 +82,9 @@ k_evaluate(const FParams P, const Rule R, int64_t n,
     extern __shared__ double lds[];          // Dbuf[D][64], part[W][5][64]
 
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    // the wave index is the same on every lane: say so, so that the unit
+    // loop, the point signs and the pair decoding stay in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int W = blockDim.x >> 6;
     const int64_t r0 = (int64_t)blockIdx.x * 64 + lane;
     const int64_t r = r0 < n ? r0 : n - 1;   // tail lanes recompute the last
@@ -199,6 +201,21 @@ k_evaluate(const FParams P, const Rule R, int64_t n,
         }
         K[r0] = (uint8_t)best;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Integrand values at n points x[k * ld + i] (one lane per point)
+// ---------------------------------------------------------------------------
+template <int FAM, int D>
+__global__ void __launch_bounds__(256)
+k_fvalues(const FParams P, int64_t n, const double *__restrict__ x,
+          int64_t ld, double *__restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double xi[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) xi[k] = x[k * ld + i];
+    y[i] = integrand<FAM, D>(xi, P);
 }
 
 // ---------------------------------------------------------------------------
@@ -577,6 +594,43 @@ static EvalKernel eval_kernel(int family, int d) {
     case PG_MONOMIAL: return eval_table<PG_MONOMIAL>(d);
     default: return nullptr;
     }
+}
+
+typedef void (*FvalKernel)(const FParams, int64_t, const double *, int64_t,
+                           double *);
+
+template <int FAM>
+static FvalKernel fval_table(int d) {
+    switch (d) {
+    case 2: return k_fvalues<FAM, 2>;
+    case 3: return k_fvalues<FAM, 3>;
+    case 4: return k_fvalues<FAM, 4>;
+    case 5: return k_fvalues<FAM, 5>;
+    case 6: return k_fvalues<FAM, 6>;
+    case 7: return k_fvalues<FAM, 7>;
+    case 8: return k_fvalues<FAM, 8>;
+    case 9: return k_fvalues<FAM, 9>;
+    case 10: return k_fvalues<FAM, 10>;
+    default: return nullptr;
+    }
+}
+
+hipError_t launch_fvalues(hipStream_t st, int family, int d, const FParams &P,
+                          int64_t n, const double *x, int64_t ld, double *y) {
+    FvalKernel k = nullptr;
+    switch (family) {
+    case PG_PRODUCT_PEAK: k = fval_table<PG_PRODUCT_PEAK>(d); break;
+    case PG_GAUSSIAN: k = fval_table<PG_GAUSSIAN>(d); break;
+    case PG_OSCILLATORY: k = fval_table<PG_OSCILLATORY>(d); break;
+    case PG_CORNER_PEAK: k = fval_table<PG_CORNER_PEAK>(d); break;
+    case PG_MONOMIAL: k = fval_table<PG_MONOMIAL>(d); break;
+    default: break;
+    }
+    if (!k) return hipErrorInvalidValue;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       P, n, x, ld, y);
+    return hipGetLastError();
 }
 
 bool evaluate_supported(int family, int d) {

@@ -51,6 +51,22 @@ def _params(family, d, seed):
 
 
 # ---------------------------------------------------------------------------
+# The integrands alone
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("family,d", [("product_peak", 3), ("gaussian", 5),
+                                      ("oscillatory", 8), ("corner_peak", 6)])
+def test_integrand_values(ctx, family, d):
+    _say("integrand", family, d)
+    p = _params(family, d, seed=21)
+    x = np.random.default_rng(d).uniform(0, 1, size=(d, 3000))
+    y = ctx.integrand_values(family, p, _dev(x)).cpu().numpy()
+    ref = np.array([oracle.f(family, p, x[:, i]) for i in range(x.shape[1])])
+    # a few ulps of each function, amplified by its argument's rounding
+    np.testing.assert_allclose(y, ref, rtol=2e-13, atol=0)
+
+
+# ---------------------------------------------------------------------------
 # EVALUATE
 # ---------------------------------------------------------------------------
 
