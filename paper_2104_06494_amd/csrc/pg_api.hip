@@ -35,9 +35,9 @@ struct pg_context {
     uint8_t *K = nullptr, *A = nullptr, *A2 = nullptr;
     SegPartials part{};
     uint32_t *off = nullptr;
-    double *blk_cnt = nullptr, *blk_ae = nullptr;
+    double *search_part = nullptr;
     Totals *dtot = nullptr, *htot = nullptr;
-    TrialTotals *dtrial = nullptr, *htrial = nullptr;
+    SearchState *dstate = nullptr, *hstate = nullptr;
     std::vector<hipEvent_t> events;
     std::string err;
     // live list left by the last pg_integrate
@@ -52,7 +52,7 @@ constexpr size_t ALIGN = 256;
 struct Layout {
     size_t lo[2], w[2], V, E, Vp, K, A, A2;
     size_t pv, pe, pav, pae, pmin, pmax, pcnt, off;
-    size_t blk_cnt, blk_ae, dtot, dtrial, total;
+    size_t search_part, dtot, dstate, total;
     int64_t nseg;
 };
 
@@ -86,10 +86,9 @@ Layout layout(int dim_max, int64_t cap) {
     L.pmax = bump(at, sizeof(double) * L.nseg);
     L.pcnt = bump(at, sizeof(uint32_t) * L.nseg);
     L.off = bump(at, sizeof(uint32_t) * L.nseg);
-    L.blk_cnt = bump(at, sizeof(double) * TRIAL_M * TRIAL_BLOCKS);
-    L.blk_ae = bump(at, sizeof(double) * TRIAL_M * TRIAL_BLOCKS);
+    L.search_part = bump(at, sizeof(double) * 2 * TRIAL_M * TRIAL_BLOCKS);
     L.dtot = bump(at, sizeof(Totals));
-    L.dtrial = bump(at, sizeof(TrialTotals));
+    L.dstate = bump(at, sizeof(SearchState));
     L.total = (at + ALIGN - 1) / ALIGN * ALIGN;
     return L;
 }
@@ -213,70 +212,67 @@ int sync_tot(pg_context *ctx, Totals *out) {
     return PG_OK;
 }
 
-// THRESHOLD-CLASSIFY (Algorithm 3) on the list (E, A_rel) of n regions. The
-// search is sequential -- each trial picks the next threshold from the
-// previous outcome -- but the thresholds it can reach in the next
-// TRIAL_DEPTH trials form a binary tree that depends only on the current
-// threshold and min/max E, so one pass over the list tests all of them and
-// the host then walks the tree exactly as the sequential search would.
+// THRESHOLD-CLASSIFY (Algorithm 3) on the list (E, A_rel) of n regions; its
+// state lives on the device (see k_trial_walk). Passes are queued in
+// batches of 3, 5 and 8 (most searches end in the first) and the host
+// waits once per batch; passes after the search has ended return at once.
+// With `count`, the count pass of the accepted threshold (segment counts,
+// offsets and sums of the surviving regions, into ctx->dtot) is queued
+// behind each batch, so the same wait also delivers the compaction's
+// inputs.
+constexpr int SEARCH_BATCHES[3] = {3, 5, 8};
+
 struct SearchOut {
     int ok = 0, trials = 0;
     double t = -HUGE_VAL;
 };
 
+struct CountReq {
+    int paired;
+    const double *V;
+    Totals *tot;     // host copy of the count totals (when ok)
+};
+
 int search(pg_context *ctx, int64_t n, const double *E, const uint8_t *A_rel,
            double v_tot, double e_tot, double e_it, double tau, int mem,
-           double mn, double mx, SearchOut *out) {
+           const CountReq *count, SearchOut *out) {
     const double e_b = e_tot - tau * std::fabs(v_tot);
     const double allowance = e_it - e_b;      // = tau |v_tot| - e_f
-    double P_max = 0.25;
-    double t = e_it / (double)n;
-    int last_dir = 0, dir_changes = 0, trials = 0;
-    double thr[TRIAL_M];
+    const int max_passes = (THR_MAX_TRIALS + TRIAL_DEPTH - 1) / TRIAL_DEPTH;
+    hipStream_t st = ctx->stream;
     *out = SearchOut{};
-    for (;;) {
-        thr[0] = t;
-        for (int i = 0; 2 * i + 2 < TRIAL_M; ++i) {
-            thr[2 * i + 1] = thr[i] + (mx - thr[i]) / 2.0;     // raise
-            thr[2 * i + 2] = thr[i] - (thr[i] - mn) / 2.0;     // lower
+    // min / max E were left in ctx->dtot by the pass that preceded the call
+    HIP_OR_FAIL(ctx, launch_search_init(st, ctx->dstate, n, e_it, allowance,
+                                        mem, ctx->dtot));
+    int passes = 0;
+    for (int bi = 0; bi < 3 && passes < max_passes; ++bi) {
+        const int batch = std::min(SEARCH_BATCHES[bi], max_passes - passes);
+        for (int k = 0; k < batch; ++k)
+            HIP_OR_FAIL(ctx, launch_search_pass(st, n, E, A_rel, ctx->dstate,
+                                                ctx->search_part));
+        passes += batch;
+        if (count) {
+            HIP_OR_FAIL(ctx, launch_seg_count(st, n, count->paired, 0.0,
+                                              count->V, E, A_rel, ctx->dstate,
+                                              ctx->part));
+            HIP_OR_FAIL(ctx, launch_reduce_scan(st, seg_count(n, count->paired),
+                                                ctx->part, ctx->off,
+                                                ctx->dtot));
+            HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->htot, ctx->dtot, sizeof(Totals),
+                                            hipMemcpyDeviceToHost, st));
         }
-        HIP_OR_FAIL(ctx, launch_trials(ctx->stream, n, E, A_rel, thr,
-                                       ctx->blk_cnt, ctx->blk_ae,
-                                       ctx->dtrial));
-        HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->htrial, ctx->dtrial,
-                                        sizeof(TrialTotals),
-                                        hipMemcpyDeviceToHost, ctx->stream));
-        HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
-        const TrialTotals &T = *ctx->htrial;
-        int node = 0;
-        for (int level = 0; level < TRIAL_DEPTH; ++level) {
-            if (trials >= 64) { out->trials = trials; return PG_OK; }
-            const double tt = thr[node];
-            ++trials;
-            const double s_abar = (double)n - T.cnt[node];
-            const double e_abar = e_it - T.ae[node];
-            int dir;
-            if (s_abar > 0.5 * (double)n) {
-                if (e_abar <= P_max * allowance) {
-                    out->ok = 1;
-                    out->t = tt;
-                    out->trials = trials;
-                    return PG_OK;
-                }
-                dir = -1;                         // accuracy failed: lower t
-            } else {
-                dir = +1;                         // memory failed: raise t
-            }
-            if (last_dir != 0 && dir != last_dir) {
-                ++dir_changes;
-                if (mem) P_max = std::min(P_max + 0.10, 0.95);
-                if (dir_changes >= 10) { out->trials = trials; return PG_OK; }
-            }
-            last_dir = dir;
-            t = dir > 0 ? tt + (mx - tt) / 2.0 : tt - (tt - mn) / 2.0;
-            node = dir > 0 ? 2 * node + 1 : 2 * node + 2;
-        }
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->hstate, ctx->dstate,
+                                        sizeof(SearchState),
+                                        hipMemcpyDeviceToHost, st));
+        HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
+        if (ctx->hstate->done) break;
     }
+    const SearchState &S = *ctx->hstate;
+    out->ok = S.done && S.ok;
+    out->t = out->ok ? S.t_acc : -HUGE_VAL;
+    out->trials = S.trials;
+    if (count && out->ok) *count->tot = *ctx->htot;
+    return PG_OK;
 }
 
 int validate_list(pg_context *ctx, int64_t n, int64_t ld) {
@@ -344,7 +340,7 @@ int pg_context_create(int device, int dim_max, int64_t capacity,
     }
     ctx->stream = (hipStream_t)stream;      // NULL: the null stream
     if (hipHostMalloc((void **)&ctx->htot, sizeof(Totals), 0) != hipSuccess ||
-        hipHostMalloc((void **)&ctx->htrial, sizeof(TrialTotals), 0) !=
+        hipHostMalloc((void **)&ctx->hstate, sizeof(SearchState), 0) !=
             hipSuccess) {
         pg_context_destroy(ctx);
         return PG_ENOMEM;
@@ -368,10 +364,9 @@ int pg_context_create(int device, int dim_max, int64_t capacity,
     ctx->part.emax = (double *)(b + L.pmax);
     ctx->part.cnt = (uint32_t *)(b + L.pcnt);
     ctx->off = (uint32_t *)(b + L.off);
-    ctx->blk_cnt = (double *)(b + L.blk_cnt);
-    ctx->blk_ae = (double *)(b + L.blk_ae);
+    ctx->search_part = (double *)(b + L.search_part);
     ctx->dtot = (Totals *)(b + L.dtot);
-    ctx->dtrial = (TrialTotals *)(b + L.dtrial);
+    ctx->dstate = (SearchState *)(b + L.dstate);
     *out = ctx;
     return PG_OK;
 }
@@ -382,7 +377,7 @@ void pg_context_destroy(pg_context *ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
     if (ctx->htot) (void)hipHostFree(ctx->htot);
-    if (ctx->htrial) (void)hipHostFree(ctx->htrial);
+    if (ctx->hstate) (void)hipHostFree(ctx->hstate);
     if (ctx->own_ws && ctx->ws) (void)hipFree(ctx->ws);
     delete ctx;
 }
@@ -471,15 +466,12 @@ int pg_threshold_search(pg_context *ctx, int64_t n, const double *E,
     HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
     // min / max of E over the whole list (the count pass over E records them)
     HIP_OR_FAIL(ctx, launch_seg_count(ctx->stream, n, 0, -HUGE_VAL, E, E,
-                                      A_rel, ctx->part));
+                                      A_rel, nullptr, ctx->part));
     HIP_OR_FAIL(ctx, launch_reduce_scan(ctx->stream, seg_count(n, 0),
                                         ctx->part, ctx->off, ctx->dtot));
-    Totals T;
-    rc = sync_tot(ctx, &T);
-    if (rc) return rc;
     SearchOut so;
     rc = search(ctx, n, E, A_rel, v_tot, e_tot, e_it, rel_tol,
-                memory_pressure, T.emin, T.emax, &so);
+                memory_pressure, nullptr, &so);
     if (rc) return rc;
     *ok = so.ok;
     *t = so.ok ? so.t : NAN;
@@ -508,7 +500,7 @@ int pg_filter_split(pg_context *ctx, int dim, int64_t n, const double *lo,
         return fail(ctx, PG_EINVAL, "NULL array");
     HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
     HIP_OR_FAIL(ctx, launch_seg_count(ctx->stream, n, 0, 0.0, V, nullptr, A,
-                                      ctx->part));
+                                      nullptr, ctx->part));
     HIP_OR_FAIL(ctx, launch_reduce_scan(ctx->stream, seg_count(n, 0),
                                         ctx->part, ctx->off, ctx->dtot));
     Totals T;
@@ -686,23 +678,21 @@ int pg_integrate(pg_context *ctx, const pg_integrand *f, const double *lo,
             if (trig_a || trig_b) {
                 ++res.threshold_calls;
                 rec.thr_invoked = 1;
+                Totals T2;
+                const CountReq cr{paired, ctx->V, &T2};
                 RUN_RC(search(ctx, n, ctx->E, ctx->A, v_tot, e_tot, e, tau,
-                              trig_b ? 1 : 0, T.emin, T.emax, &so));
+                              trig_b ? 1 : 0, &cr, &so));
                 res.threshold_trials += so.trials;
                 rec.thr_ok = so.ok;
                 rec.thr_trials = so.trials;
                 if (so.ok) {
                     rec.t = so.t;
-                    RUN_FAIL(launch_seg_count(st, n, paired, so.t, ctx->V,
-                                              ctx->E, ctx->A, ctx->part));
-                    RUN_FAIL(launch_reduce_scan(st, nseg, ctx->part, ctx->off,
-                                                ctx->dtot));
-                    Totals T2;
-                    RUN_RC(sync_tot(ctx, &T2));
                     av = T2.av;
                     ae = T2.ae;
                     n_act = (int64_t)T2.cnt;
                 }
+                // after a failed search the queued count pass recounted
+                // A_rel, so the segment offsets equal the classify pass's
             }
             if (!so.ok && 2 * n_rel > cap) {
                 status = PG_MEMORY_EXHAUSTED;

@@ -14,8 +14,9 @@ namespace pg {
 // regions; segments never straddle the two halves of a paired list.
 constexpr int SEG = 2048;
 constexpr int LIST_THREADS = 256;
-// Blocks of the threshold-trial pass (grid-stride, fixed for determinism).
-constexpr int TRIAL_BLOCKS = 1024;
+// Blocks (at most) and threads per block of a threshold-trial pass.
+constexpr int TRIAL_BLOCKS = 256;
+constexpr int TRIAL_THREADS = 1024;
 // Thresholds tested per trial pass: a complete binary tree of depth 4 of the
 // search's possible next steps.
 constexpr int TRIAL_DEPTH = 4;
@@ -77,10 +78,22 @@ struct Totals {
     double pad;
 };
 
-// Per-candidate sums of one threshold trial pass.
-struct TrialTotals {
-    double cnt[TRIAL_M];   // active regions under each candidate threshold
-    double ae[TRIAL_M];    // sum of E over those regions
+// Limits of the threshold search (the paper bounds it without numbers).
+constexpr int THR_MAX_TRIALS = 64;
+constexpr int THR_MAX_DIRCHG = 10;
+
+// State of one threshold search (Algorithm 3), kept in device memory.
+struct SearchState {
+    int64_t n;            // s_it
+    double e_it;          // error of the regions being processed
+    double allowance;     // e_it - e_b = tau |v_tot| - e_f
+    double mn, mx;        // min / max of E over the list
+    double t;             // next threshold to try (root of the next pass)
+    double P_max;
+    double t_acc;         // accepted threshold
+    int mem;              // searching under memory pressure
+    int last_dir, dir_changes, trials;
+    int done, ok;
 };
 
 // ---- launchers (pg_kernels.hip); all queue on `st` -----------------------
@@ -100,14 +113,22 @@ hipError_t launch_classify(hipStream_t st, int64_t n, int paired,
                            const double *V, double *E, const double *Vp,
                            double tau, int relerr, uint8_t *A,
                            SegPartials part);
+// S != nullptr: t is the search's accepted threshold (none if it failed).
 hipError_t launch_seg_count(hipStream_t st, int64_t n, int paired, double t,
                             const double *V, const double *E,
-                            const uint8_t *A_rel, SegPartials part);
+                            const uint8_t *A_rel, const SearchState *S,
+                            SegPartials part);
 hipError_t launch_reduce_scan(hipStream_t st, int64_t nseg, SegPartials part,
                               uint32_t *offsets, Totals *tot);
-hipError_t launch_trials(hipStream_t st, int64_t n, const double *E,
-                         const uint8_t *A_rel, const double *thr,
-                         double *blk_cnt, double *blk_ae, TrialTotals *tot);
+hipError_t launch_search_init(hipStream_t st, SearchState *S, int64_t n,
+                              double e_it, double allowance, int mem,
+                              const Totals *minmax);
+// One pass (TRIAL_DEPTH trials) of the search: k_trials + k_trial_walk; a
+// no-op once the search has ended. blk_part holds 2 TRIAL_M x TRIAL_BLOCKS
+// doubles.
+hipError_t launch_search_pass(hipStream_t st, int64_t n, const double *E,
+                              const uint8_t *A_rel, SearchState *S,
+                              double *blk_part);
 hipError_t launch_compact_split(hipStream_t st, int d, int64_t n, int paired,
                                 double t, const uint8_t *A_rel,
                                 const double *E, const double *V,

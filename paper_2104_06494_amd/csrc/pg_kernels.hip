@@ -329,10 +329,12 @@ k_classify(int64_t n, int paired, const double *__restrict__ V,
 }
 
 // Per-segment count and sums of A = A_rel AND (E > t); E == nullptr: A_rel.
+// With a search state, t is the accepted threshold (or none if it failed).
 __global__ void __launch_bounds__(LIST_THREADS)
 k_seg_count(int64_t n, int paired, double t, const double *__restrict__ V,
             const double *__restrict__ E, const uint8_t *__restrict__ A_rel,
-            SegPartials part) {
+            const SearchState *__restrict__ S, SegPartials part) {
+    if (S) t = S->ok ? S->t_acc : -__builtin_huge_val();
     int64_t s0, s1;
     seg_range(blockIdx.x, n, paired, &s0, &s1);
     Acc acc;
@@ -404,81 +406,173 @@ k_reduce_scan(int64_t nseg, SegPartials part, uint32_t *__restrict__ offsets,
 }
 
 // ---------------------------------------------------------------------------
-// THRESHOLD trials: for TRIAL_M candidate thresholds at once, the number of
-// regions that stay active (A_rel AND E > t) and the sum of their errors.
+// THRESHOLD-CLASSIFY (Algorithm 3) with its state on the device.
+//
+// The search is sequential -- each trial picks the next threshold from the
+// previous outcome -- but the thresholds it can reach in its next
+// TRIAL_DEPTH trials form a complete binary tree that depends only on the
+// current threshold and on min/max E (raise: t + (max - t)/2, lower:
+// t - (t - min)/2). One pass over the list counts, for all TRIAL_M nodes of
+// that tree, the regions that stay active (A_rel AND E > t) and the sum of
+// their errors; the tree is then walked exactly as the sequential search
+// would walk it, which leaves the next root in the state.
 // ---------------------------------------------------------------------------
-struct Thr {
-    double t[TRIAL_M];
-};
+__device__ inline void build_tree(const SearchState &S, double *thr) {
+    thr[0] = S.t;
+#pragma unroll
+    for (int i = 0; 2 * i + 2 < TRIAL_M; ++i) {
+        thr[2 * i + 1] = thr[i] + (S.mx - thr[i]) / 2.0;    // raise
+        thr[2 * i + 2] = thr[i] - (thr[i] - S.mn) / 2.0;    // lower
+    }
+}
 
-__global__ void __launch_bounds__(LIST_THREADS)
+__global__ void k_search_init(SearchState *__restrict__ S, int64_t n,
+                              double e_it, double allowance, int mem,
+                              const Totals *__restrict__ minmax) {
+    if (threadIdx.x != 0) return;
+    SearchState s{};
+    s.n = n;
+    s.e_it = e_it;
+    s.allowance = allowance;
+    s.mem = mem;
+    s.mn = minmax->emin;
+    s.mx = minmax->emax;
+    s.t = e_it / (double)n;
+    s.P_max = 0.25;
+    s.t_acc = -__builtin_huge_val();
+    *S = s;
+}
+
+// Walks up to TRIAL_DEPTH levels of the tree (Algorithm 3's loop) given the
+// totals of a pass: tot[m] regions stay active under node m's threshold and
+// tot[TRIAL_M + m] is the sum of their errors.
+__device__ void walk_tree(SearchState &st, const double *tot) {
+    double thr[TRIAL_M];
+    build_tree(st, thr);
+    int node = 0;
+    for (int level = 0; level < TRIAL_DEPTH; ++level) {
+        if (st.trials >= THR_MAX_TRIALS) { st.done = 1; return; }
+        const double tt = thr[node];
+        ++st.trials;
+        const double s_abar = (double)st.n - tot[node];
+        const double e_abar = st.e_it - tot[TRIAL_M + node];
+        int dir;
+        if (s_abar > 0.5 * (double)st.n) {
+            if (e_abar <= st.P_max * st.allowance) {
+                st.done = 1;
+                st.ok = 1;
+                st.t_acc = tt;
+                return;
+            }
+            dir = -1;                           // accuracy failed: lower t
+        } else {
+            dir = +1;                           // memory failed: raise t
+        }
+        if (st.last_dir != 0 && dir != st.last_dir) {
+            ++st.dir_changes;
+            if (st.mem) st.P_max = fmin(st.P_max + 0.10, 0.95);
+            if (st.dir_changes >= THR_MAX_DIRCHG) { st.done = 1; return; }
+        }
+        st.last_dir = dir;
+        st.t = dir > 0 ? tt + (st.mx - tt) / 2.0 : tt - (tt - st.mn) / 2.0;
+        node = dir > 0 ? 2 * node + 1 : 2 * node + 2;
+    }
+}
+
+// One pass over the list for the TRIAL_M thresholds of the current tree.
+// Counts come from wave ballots (already wave totals, in scalar registers);
+// the error sums are reduced through LDS (each wave writes its lanes' sums
+// and TRIAL_M lanes add one row each) and then over the waves in order.
+// The list is walked in wave-sized chunks so the loop is wave-uniform. The
+// block sums go to k_trial_walk; the kernel boundary between the two makes
+// them visible without any device-wide fence inside a kernel.
+__global__ void __launch_bounds__(TRIAL_THREADS)
 k_trials(int64_t n, const double *__restrict__ E,
-         const uint8_t *__restrict__ A_rel, const Thr T,
-         double *__restrict__ blk_cnt, double *__restrict__ blk_ae) {
+         const uint8_t *__restrict__ A_rel, const SearchState *__restrict__ S,
+         double *__restrict__ blk_part) {
+    constexpr int NW = TRIAL_THREADS / 64;
+    __shared__ double rows[NW][TRIAL_M][65];    // padded: no bank conflicts
+    __shared__ double wsum[NW][2 * TRIAL_M];
+    if (S->done) return;                        // same for every block
+    double thr[TRIAL_M];
+    build_tree(*S, thr);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint32_t cnt[TRIAL_M];
     double ae[TRIAL_M];
 #pragma unroll
     for (int m = 0; m < TRIAL_M; ++m) { cnt[m] = 0; ae[m] = 0.0; }
-    const int64_t stride = (int64_t)gridDim.x * LIST_THREADS;
-    for (int64_t i = (int64_t)blockIdx.x * LIST_THREADS + threadIdx.x; i < n;
-         i += stride) {
-        const double e = E[i];
-        const bool a = A_rel[i] != 0;
+    const int64_t stride = (int64_t)gridDim.x * TRIAL_THREADS;
+    for (int64_t i0 = (int64_t)blockIdx.x * TRIAL_THREADS + wave * 64; i0 < n;
+         i0 += stride) {
+        const int64_t i = i0 + lane;
+        const bool valid = i < n;
+        const double e = valid ? E[i] : 0.0;
+        const bool a = valid && A_rel[i] != 0;
 #pragma unroll
         for (int m = 0; m < TRIAL_M; ++m) {
-            const bool act = a && e > T.t[m];
-            cnt[m] += act ? 1u : 0u;
+            const bool act = a && e > thr[m];
+            cnt[m] += (uint32_t)__popcll(__ballot(act));
             ae[m] += act ? e : 0.0;
         }
     }
-    __shared__ double wred[2][LIST_THREADS / 64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int m = 0; m < TRIAL_M; ++m) {
-        double c = (double)cnt[m], s = ae[m];
-        for (int off = 32; off >= 1; off >>= 1) {
-            c += __shfl_xor(c, off);
-            s += __shfl_xor(s, off);
-        }
-        __syncthreads();
-        if (lane == 0) { wred[0][wave] = c; wred[1][wave] = s; }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double tc = 0.0, ts = 0.0;
-            for (int q = 0; q < LIST_THREADS / 64; ++q) {
-                tc += wred[0][q];
-                ts += wred[1][q];
-            }
-            blk_cnt[(int64_t)m * gridDim.x + blockIdx.x] = tc;
-            blk_ae[(int64_t)m * gridDim.x + blockIdx.x] = ts;
-        }
+#pragma unroll
+    for (int m = 0; m < TRIAL_M; ++m) rows[wave][m][lane] = ae[m];
+    __syncthreads();
+    if (lane < TRIAL_M) {
+        double t = 0.0;
+        for (int l = 0; l < 64; ++l) t += rows[wave][lane][l];
+        wsum[wave][TRIAL_M + lane] = t;
+        wsum[wave][lane] = (double)cnt[0];
+#pragma unroll
+        for (int m = 1; m < TRIAL_M; ++m)
+            if (lane == m) wsum[wave][lane] = (double)cnt[m];
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * TRIAL_M) {
+        double t = 0.0;
+        for (int q = 0; q < NW; ++q) t += wsum[q][threadIdx.x];
+        blk_part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
     }
 }
 
+// Adds the block sums of one pass in a fixed order and walks the tree.
 __global__ void __launch_bounds__(SCAN_THREADS)
-k_trial_reduce(int nblk, const double *__restrict__ blk_cnt,
-               const double *__restrict__ blk_ae, TrialTotals *__restrict__ tot) {
-    // one wave per candidate, blocks summed in a fixed tree
-    const int lane = threadIdx.x & 63, m = threadIdx.x >> 6;
-    if (m >= TRIAL_M) return;
-    double c = 0.0, s = 0.0;
-    for (int b = lane; b < nblk; b += 64) {
-        c += blk_cnt[(int64_t)m * nblk + b];
-        s += blk_ae[(int64_t)m * nblk + b];
+k_trial_walk(int nblk, const double *__restrict__ blk_part,
+             SearchState *__restrict__ S) {
+    __shared__ double tot[2 * TRIAL_M];
+    if (S->done) return;
+    {
+        // 16 threads per sum over a fixed stride of blocks (loads unrolled),
+        // then a fixed shuffle tree over the 16
+        const int v = threadIdx.x >> 4, g = threadIdx.x & 15;
+        double t = 0.0;
+        if (v < 2 * TRIAL_M) {
+            const double *src = blk_part + (int64_t)v * nblk;
+#pragma unroll 16
+            for (int b = g; b < nblk; b += 16) t += src[b];
+        }
+        for (int off = 8; off >= 1; off >>= 1) t += __shfl_xor(t, off);
+        if (v < 2 * TRIAL_M && g == 0) tot[v] = t;
     }
-    for (int off = 32; off >= 1; off >>= 1) {
-        c += __shfl_xor(c, off);
-        s += __shfl_xor(s, off);
-    }
-    if (lane == 0) {
-        tot->cnt[m] = c;
-        tot->ae[m] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        SearchState st = *S;
+        walk_tree(st, tot);
+        *S = st;
     }
 }
 
 // ---------------------------------------------------------------------------
-// FILTER + parent update + SPLIT: stable compaction by ballot prefix within
-// each segment, segment bases from the exclusive scan.
+// FILTER + parent update + SPLIT: stable compaction of a segment of up to SEG
+// regions by one block. The flags of all SEG / LIST_THREADS rounds are read
+// first (region s0 + r * LIST_THREADS + tid in round r, coalesced), their
+// wave ballots give the prefix in (round, wave) order after one barrier, and
+// the survivors are then copied and bisected; the segment's base comes from
+// the exclusive scan of the segment counts.
 // ---------------------------------------------------------------------------
+constexpr int CS_ROUNDS = SEG / LIST_THREADS;
+
 __global__ void __launch_bounds__(LIST_THREADS)
 k_compact_split(int d, int64_t n, int paired, double t,
                 const uint8_t *__restrict__ A_rel, const double *__restrict__ E,
@@ -488,45 +582,46 @@ k_compact_split(int d, int64_t n, int paired, double t,
                 int64_t na, double *__restrict__ lo_out,
                 double *__restrict__ w_out, int64_t ld_out,
                 double *__restrict__ Vp) {
-    __shared__ uint32_t wtot[LIST_THREADS / 64];
+    constexpr int NW = LIST_THREADS / 64;
+    __shared__ uint32_t wcnt[CS_ROUNDS * NW];
     int64_t s0, s1;
     seg_range(blockIdx.x, n, paired, &s0, &s1);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int64_t base = offsets[blockIdx.x];
-    for (int64_t i0 = s0; i0 < s1; i0 += LIST_THREADS) {
-        const int64_t i = i0 + threadIdx.x;
-        const bool act = i < s1 && A_rel[i] && (!E || E[i] > t);
-        const uint64_t mask = __ballot(act);
-        const uint32_t pre = __popcll(mask & ((1ull << lane) - 1ull));
-        if (lane == 0) wtot[wave] = __popcll(mask);
-        __syncthreads();
-        uint32_t wpre = 0, total = 0;
-        for (int q = 0; q < LIST_THREADS / 64; ++q) {
-            if (q < wave) wpre += wtot[q];
-            total += wtot[q];
+    const uint64_t below = (1ull << lane) - 1ull;
+    uint32_t act = 0, pre[CS_ROUNDS];
+#pragma unroll
+    for (int r = 0; r < CS_ROUNDS; ++r) {
+        const int64_t i = s0 + r * LIST_THREADS + threadIdx.x;
+        const bool a = i < s1 && A_rel[i] && (!E || E[i] > t);
+        const uint64_t mask = __ballot(a);
+        pre[r] = __popcll(mask & below);
+        act |= (a ? 1u : 0u) << r;
+        if (lane == 0) wcnt[r * NW + wave] = __popcll(mask);
+    }
+    __syncthreads();
+    const int64_t base = offsets[blockIdx.x];
+    uint32_t run = 0;                       // survivors before round r
+#pragma unroll
+    for (int r = 0; r < CS_ROUNDS; ++r) {
+        uint32_t rbase = run;
+        for (int q = 0; q < NW; ++q) {
+            if (q < wave) rbase += wcnt[r * NW + q];
+            run += wcnt[r * NW + q];
         }
-        if (act) {
-            const int64_t j = base + wpre + pre;
-            const int ax = K[i];
-            for (int k = 0; k < d; ++k) {
-                const double l = lo[k * ld_in + i], ww = w[k * ld_in + i];
-                if (k == ax) {
-                    const double half = ww * 0.5;
-                    lo_out[k * ld_out + j] = l;
-                    w_out[k * ld_out + j] = half;
-                    lo_out[k * ld_out + j + na] = l + half;
-                    w_out[k * ld_out + j + na] = half;
-                } else {
-                    lo_out[k * ld_out + j] = l;
-                    w_out[k * ld_out + j] = ww;
-                    lo_out[k * ld_out + j + na] = l;
-                    w_out[k * ld_out + j + na] = ww;
-                }
-            }
-            Vp[j] = V[i];
+        if (!((act >> r) & 1u)) continue;
+        const int64_t i = s0 + r * LIST_THREADS + threadIdx.x;
+        const int64_t j = base + rbase + pre[r];
+        const int ax = K[i];
+        for (int k = 0; k < d; ++k) {
+            const double l = lo[k * ld_in + i], ww = w[k * ld_in + i];
+            const double half = ww * 0.5;
+            const bool sp = k == ax;
+            lo_out[k * ld_out + j] = l;
+            w_out[k * ld_out + j] = sp ? half : ww;
+            lo_out[k * ld_out + j + na] = sp ? l + half : l;
+            w_out[k * ld_out + j + na] = sp ? half : ww;
         }
-        base += total;
-        __syncthreads();
+        Vp[j] = V[i];
     }
 }
 
@@ -687,10 +782,11 @@ hipError_t launch_classify(hipStream_t st, int64_t n, int paired,
 
 hipError_t launch_seg_count(hipStream_t st, int64_t n, int paired, double t,
                             const double *V, const double *E,
-                            const uint8_t *A_rel, SegPartials part) {
+                            const uint8_t *A_rel, const SearchState *S,
+                            SegPartials part) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_seg_count, dim3((unsigned)seg_count(n, paired)),
-                       dim3(LIST_THREADS), 0, st, n, paired, t, V, E, A_rel,
+                       dim3(LIST_THREADS), 0, st, n, paired, t, V, E, A_rel, S,
                        part);
     return hipGetLastError();
 }
@@ -702,20 +798,31 @@ hipError_t launch_reduce_scan(hipStream_t st, int64_t nseg, SegPartials part,
     return hipGetLastError();
 }
 
-hipError_t launch_trials(hipStream_t st, int64_t n, const double *E,
-                         const uint8_t *A_rel, const double *thr,
-                         double *blk_cnt, double *blk_ae, TrialTotals *tot) {
-    Thr T;
-    for (int m = 0; m < TRIAL_M; ++m) T.t[m] = thr[m];
-    int64_t blocks = (n + LIST_THREADS - 1) / LIST_THREADS;
+hipError_t launch_search_init(hipStream_t st, SearchState *S, int64_t n,
+                              double e_it, double allowance, int mem,
+                              const Totals *minmax) {
+    hipLaunchKernelGGL(k_search_init, dim3(1), dim3(64), 0, st, S, n, e_it,
+                       allowance, mem, minmax);
+    return hipGetLastError();
+}
+
+int trial_blocks(int64_t n) {
+    int64_t blocks = (n + TRIAL_THREADS - 1) / TRIAL_THREADS;
     if (blocks > TRIAL_BLOCKS) blocks = TRIAL_BLOCKS;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_trials, dim3((unsigned)blocks), dim3(LIST_THREADS), 0,
-                       st, n, E, A_rel, T, blk_cnt, blk_ae);
+    return (int)blocks;
+}
+
+hipError_t launch_search_pass(hipStream_t st, int64_t n, const double *E,
+                              const uint8_t *A_rel, SearchState *S,
+                              double *blk_part) {
+    const int blocks = trial_blocks(n);
+    hipLaunchKernelGGL(k_trials, dim3((unsigned)blocks), dim3(TRIAL_THREADS), 0,
+                       st, n, E, A_rel, S, blk_part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_trial_reduce, dim3(1), dim3(SCAN_THREADS), 0, st,
-                       (int)blocks, blk_cnt, blk_ae, tot);
+    hipLaunchKernelGGL(k_trial_walk, dim3(1), dim3(SCAN_THREADS), 0, st,
+                       blocks, blk_part, S);
     return hipGetLastError();
 }
 
