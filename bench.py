@@ -46,7 +46,7 @@ PEAK_FP64_TFLOPS = 78.6
 
 def _kernel_sha():
     import hashlib
-    path = os.path.join(ROOT, "paper_2104_06494_amd", "csrc", "pg_kernels.hip")
+    path = os.path.join(ROOT, "paper_2104_06494_amd", "csrc", "pg_evaluate.hip")
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
@@ -124,9 +124,54 @@ def headline(args):
             "eval_evals_per_s": regions * npts / (eval_ms * 1e-3),
         },
     }
+    if not args.no_batched:
+        out["batched"] = batched(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)
+
+
+def batched(args):
+    """The 1024 d=6 corner-peak integrals (per-integral a ~ U[0,2]^6 and
+    rel_tol 10^U[-7,-4], seed 4, 2^6 initial grid, 2^21-region cap each)
+    as one batched run and as 1024 single runs one after another, on the
+    same context. Both give the same results; evals/s and wall time of
+    each (one untimed warm-up of the batched run first)."""
+    import torch
+    import paper_2104_06494_amd as pg
+    import workloads as W
+    from workloads import closed_forms as cf
+
+    wl = W.corner_peak_batch_d6()
+    slots = args.batch_slots
+    ctx = pg.Context(capacity=slots * wl.max_regions, dim_max=wl.d)
+    ctx.integrate_batch_workload(wl, count=min(wl.B, 2 * slots))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rb = ctx.integrate_batch_workload(wl)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rp = [ctx.integrate_workload(wl.instance(b)) for b in range(wl.B)]
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    fe = sum(r.fevals for r in rb)
+    same = sum((a.status, a.iterations, a.regions_evaluated) ==
+               (b.status, b.iterations, b.regions_evaluated) for a, b in zip(rb, rp))
+    met = 0
+    for b, r in enumerate(rb):
+        exact = cf.exact(wl.family, wl.params[b], wl.d)
+        met += abs(r.estimate - exact) <= wl.rel_tol[b] * abs(exact)
+    ctx.close()
+    return {"workload": "corner_peak_batch_d6", "B": wl.B, "slots_in_flight": slots,
+            "evals_per_s": fe / tb, "wall_ms": 1e3 * tb,
+            "plain_sequential": {"evals_per_s": fe / tp, "wall_ms": 1e3 * tp},
+            "speedup_vs_plain": tp / tb, "fevals": fe,
+            "same_schedule_as_plain": same,
+            "status_ok": sum(r.status_name == "OK" for r in rb),
+            "closed_form_met": int(met),
+            "regions_evaluated": sum(r.regions_evaluated for r in rb),
+            "max_iterations": max(r.iterations for r in rb)}
 
 
 def cpu_baseline(wl):
@@ -181,6 +226,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", choices=["headline", "integrand", "copy"], default="headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-vs-plain comparison")
+    ap.add_argument("--batch-slots", type=int, default=64,
+                    help="integrals in flight in the batched run (each "
+                         "reserves 2^21 regions of workspace)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not "

@@ -149,6 +149,24 @@ int pg_integrate(pg_context *ctx, const pg_integrand *f, const double *lo,
                  const double *hi, const pg_options *opt, pg_result *out);
 
 /*
+ * Many integrals of one family at once (B parameter vectors, row-major
+ * params[b * n_params + k], same box [lo, hi] for all), each with its own
+ * rel_tol[b] and abs_tol[b] (abs_tol may be NULL: opt->abs_tol for all).
+ * Every integral runs exactly the iteration of pg_integrate (Algorithm 2)
+ * with the options in opt, opt->max_regions being the cap of each integral;
+ * the integrals share one region list and every kernel launch. At most
+ * min(B, capacity / cap, 1024) integrals are in flight at a time; the rest
+ * start as others finish. out[b] receives integral b's result (phase_ms
+ * and the trace are not recorded). Returns PG_OK, or an error as
+ * pg_integrate does (no integral has a result then).
+ */
+int pg_integrate_batch(pg_context *ctx, int family, int dim, int B,
+                       const double *params, int n_params, const double *lo,
+                       const double *hi, const double *rel_tol,
+                       const double *abs_tol, const pg_options *opt,
+                       pg_result *out);
+
+/*
  * View of the live region list as the last pg_integrate left it: the n
  * regions of its last iteration with their V, (refined) E, split axis K and
  * rel-err flags A. Device pointers, valid until the next call that uses the

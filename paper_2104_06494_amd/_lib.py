@@ -22,7 +22,8 @@ STATUS = {0: "OK", 1: "MAX_ITERS", 2: "MEMORY_EXHAUSTED", 3: "NO_ACTIVE",
 EXPORTS = ["pg_default_options", "pg_workspace_bytes", "pg_context_create",
            "pg_context_destroy", "pg_context_set_stream", "pg_last_error",
            "pg_integrate", "pg_last_regions", "pg_evaluate", "pg_classify",
-           "pg_threshold_search", "pg_filter_split", "pg_integrand_values"]
+           "pg_threshold_search", "pg_filter_split", "pg_integrand_values",
+           "pg_integrate_batch"]
 
 
 class Integrand(C.Structure):
@@ -91,6 +92,11 @@ def load():
                                C.POINTER(C.c_double), C.POINTER(Options),
                                C.POINTER(Result)]
     L.pg_integrate.restype = C.c_int
+    dp = C.POINTER(C.c_double)
+    L.pg_integrate_batch.argtypes = [vp, C.c_int, C.c_int, C.c_int, dp, C.c_int,
+                                     dp, dp, dp, dp, C.POINTER(Options),
+                                     C.POINTER(Result)]
+    L.pg_integrate_batch.restype = C.c_int
     L.pg_last_regions.argtypes = [vp, C.POINTER(RegionsView)]
     L.pg_last_regions.restype = C.c_int
     L.pg_evaluate.argtypes = [vp, C.POINTER(Integrand), i64, vp, vp, i64, vp,

@@ -157,6 +157,53 @@ class Context:
             raise self._err(rc)
         return IntegrateResult(**r.as_dict())
 
+    def integrate_batch(self, family, d, params, rel_tol, abs_tol=None,
+                        lo=None, hi=None, init_splits=4, max_iters=100,
+                        relerr_filter=1, threshold_filter=1, max_regions=0):
+        """Algorithm 2 for B integrals of one family at once: params is
+        [B, n_params], rel_tol a scalar or [B], abs_tol None (1e-20), a
+        scalar or [B]; all share the box [lo, hi] and the options, and
+        max_regions is the cap of each. Returns a list of B results."""
+        self._bind_stream()
+        P = np.ascontiguousarray(np.atleast_2d(np.asarray(params, dtype=np.float64)))
+        B, npar = P.shape
+        rt = np.ascontiguousarray(np.broadcast_to(np.asarray(rel_tol, np.float64), (B,)))
+        lo = np.zeros(d) if lo is None else np.asarray(lo, dtype=np.float64)
+        hi = np.ones(d) if hi is None else np.asarray(hi, dtype=np.float64)
+        cp = P.ravel().ctypes.data_as(C.POINTER(C.c_double))
+        crt = rt.ctypes.data_as(C.POINTER(C.c_double))
+        clo = (C.c_double * d)(*lo.tolist())
+        chi = (C.c_double * d)(*hi.tolist())
+        at = None
+        cat = None
+        if abs_tol is not None:
+            at = np.ascontiguousarray(np.broadcast_to(np.asarray(abs_tol, np.float64), (B,)))
+            cat = at.ctypes.data_as(C.POINTER(C.c_double))
+        o = L.Options()
+        self.lib.pg_default_options(C.byref(o))
+        o.init_splits, o.max_iters = int(init_splits), int(max_iters)
+        o.relerr_filter, o.threshold_filter = int(relerr_filter), int(threshold_filter)
+        o.max_regions = int(max_regions)
+        res = (L.Result * B)()
+        fam = L.FAMILY_ID[family] if isinstance(family, str) else int(family)
+        with torch.cuda.device(self.device):
+            rc = self.lib.pg_integrate_batch(self.h, fam, int(d), int(B), cp, int(npar),
+                                             clo, chi, crt, cat, C.byref(o), res)
+        if rc < 0:
+            raise self._err(rc)
+        return [IntegrateResult(**res[b].as_dict()) for b in range(B)]
+
+    def integrate_batch_workload(self, wl, count=None):
+        """integrate_batch over a batched workload (its first `count`
+        integrals if given)."""
+        B = wl.B if count is None else int(count)
+        return self.integrate_batch(wl.family, wl.d, wl.params[:B], wl.rel_tol[:B],
+                                    wl.abs_tol[:B], wl.lo, wl.hi, init_splits=wl.init_splits,
+                                    max_iters=wl.max_iters,
+                                    relerr_filter=wl.relerr_filter,
+                                    threshold_filter=wl.threshold_filter,
+                                    max_regions=wl.max_regions)
+
     def integrate_workload(self, wl, **kw) -> IntegrateResult:
         args = dict(rel_tol=wl.rel_tol, abs_tol=wl.abs_tol,
                     init_splits=wl.init_splits, max_iters=wl.max_iters,

@@ -38,6 +38,18 @@ struct pg_context {
     double *search_part = nullptr;
     Totals *dtot = nullptr, *htot = nullptr;
     SearchState *dstate = nullptr, *hstate = nullptr;
+    // many-integral runs
+    uint32_t *inst[2] = {nullptr, nullptr};
+    BInst *b_inst = nullptr, *hb_inst = nullptr;
+    SearchState *b_state = nullptr, *hb_state = nullptr;
+    Totals *b_tot = nullptr, *hb_tot = nullptr;
+    FParams *b_table = nullptr, *hb_table = nullptr;
+    int32_t *b_order = nullptr, *hb_order = nullptr;
+    int32_t *b_new = nullptr, *hb_new = nullptr;
+    BSeg *b_segs = nullptr;
+    BCls *b_cls = nullptr;
+    double *b_tpart = nullptr;
+    int64_t nseg_max = 0;
     std::vector<hipEvent_t> events;
     std::string err;
     // live list left by the last pg_integrate
@@ -52,6 +64,8 @@ constexpr size_t ALIGN = 256;
 struct Layout {
     size_t lo[2], w[2], V, E, Vp, K, A, A2;
     size_t pv, pe, pav, pae, pmin, pmax, pcnt, off;
+    size_t inst[2], b_inst, b_state, b_tot, b_table, b_order, b_new, b_segs,
+        b_cls, b_tpart;
     size_t search_part, dtot, dstate, total;
     int64_t nseg;
 };
@@ -77,7 +91,9 @@ Layout layout(int dim_max, int64_t cap) {
     L.K = bump(at, cap);
     L.A = bump(at, cap);
     L.A2 = bump(at, cap);
-    L.nseg = 2 * ((cap + SEG - 1) / SEG) + 2;
+    // segments: single list <= 2 ceil(cap / SEG) + 2; many integrals add at
+    // most two partial segments per slot
+    L.nseg = 2 * ((cap + SEG - 1) / SEG) + 2 * BATCH_MAX_SLOTS + 2;
     L.pv = bump(at, sizeof(double) * L.nseg);
     L.pe = bump(at, sizeof(double) * L.nseg);
     L.pav = bump(at, sizeof(double) * L.nseg);
@@ -87,6 +103,16 @@ Layout layout(int dim_max, int64_t cap) {
     L.pcnt = bump(at, sizeof(uint32_t) * L.nseg);
     L.off = bump(at, sizeof(uint32_t) * L.nseg);
     L.search_part = bump(at, sizeof(double) * 2 * TRIAL_M * TRIAL_BLOCKS);
+    for (int q = 0; q < 2; ++q) L.inst[q] = bump(at, sizeof(uint32_t) * cap);
+    L.b_inst = bump(at, sizeof(BInst) * BATCH_MAX_SLOTS);
+    L.b_state = bump(at, sizeof(SearchState) * BATCH_MAX_SLOTS);
+    L.b_tot = bump(at, sizeof(Totals) * BATCH_MAX_SLOTS);
+    L.b_table = bump(at, sizeof(FParams) * BATCH_MAX_SLOTS);
+    L.b_order = bump(at, sizeof(int32_t) * BATCH_MAX_SLOTS);
+    L.b_new = bump(at, sizeof(int32_t) * BATCH_MAX_SLOTS);
+    L.b_segs = bump(at, sizeof(BSeg) * L.nseg);
+    L.b_cls = bump(at, sizeof(BCls) * L.nseg);
+    L.b_tpart = bump(at, sizeof(double) * 2 * TRIAL_M * L.nseg);
     L.dtot = bump(at, sizeof(Totals));
     L.dstate = bump(at, sizeof(SearchState));
     L.total = (at + ALIGN - 1) / ALIGN * ALIGN;
@@ -341,7 +367,19 @@ int pg_context_create(int device, int dim_max, int64_t capacity,
     ctx->stream = (hipStream_t)stream;      // NULL: the null stream
     if (hipHostMalloc((void **)&ctx->htot, sizeof(Totals), 0) != hipSuccess ||
         hipHostMalloc((void **)&ctx->hstate, sizeof(SearchState), 0) !=
-            hipSuccess) {
+            hipSuccess ||
+        hipHostMalloc((void **)&ctx->hb_inst, sizeof(BInst) * 2 * BATCH_MAX_SLOTS,
+                      0) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->hb_state,
+                      sizeof(SearchState) * BATCH_MAX_SLOTS, 0) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->hb_tot, sizeof(Totals) * BATCH_MAX_SLOTS,
+                      0) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->hb_table,
+                      sizeof(FParams) * BATCH_MAX_SLOTS, 0) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->hb_order,
+                      sizeof(int32_t) * BATCH_MAX_SLOTS, 0) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->hb_new, sizeof(int32_t) * BATCH_MAX_SLOTS,
+                      0) != hipSuccess) {
         pg_context_destroy(ctx);
         return PG_ENOMEM;
     }
@@ -365,6 +403,17 @@ int pg_context_create(int device, int dim_max, int64_t capacity,
     ctx->part.cnt = (uint32_t *)(b + L.pcnt);
     ctx->off = (uint32_t *)(b + L.off);
     ctx->search_part = (double *)(b + L.search_part);
+    for (int q = 0; q < 2; ++q) ctx->inst[q] = (uint32_t *)(b + L.inst[q]);
+    ctx->b_inst = (BInst *)(b + L.b_inst);
+    ctx->b_state = (SearchState *)(b + L.b_state);
+    ctx->b_tot = (Totals *)(b + L.b_tot);
+    ctx->b_table = (FParams *)(b + L.b_table);
+    ctx->b_order = (int32_t *)(b + L.b_order);
+    ctx->b_new = (int32_t *)(b + L.b_new);
+    ctx->b_segs = (BSeg *)(b + L.b_segs);
+    ctx->b_cls = (BCls *)(b + L.b_cls);
+    ctx->b_tpart = (double *)(b + L.b_tpart);
+    ctx->nseg_max = L.nseg;
     ctx->dtot = (Totals *)(b + L.dtot);
     ctx->dstate = (SearchState *)(b + L.dstate);
     *out = ctx;
@@ -378,6 +427,10 @@ void pg_context_destroy(pg_context *ctx) {
     for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
     if (ctx->htot) (void)hipHostFree(ctx->htot);
     if (ctx->hstate) (void)hipHostFree(ctx->hstate);
+    void *pinned[] = {ctx->hb_inst, ctx->hb_state, ctx->hb_tot, ctx->hb_table,
+                      ctx->hb_order, ctx->hb_new};
+    for (void *q : pinned)
+        if (q) (void)hipHostFree(q);
     if (ctx->own_ws && ctx->ws) (void)hipFree(ctx->ws);
     delete ctx;
 }
@@ -772,6 +825,351 @@ int pg_integrate(pg_context *ctx, const pg_integrand *f, const double *lo,
     return status;
 #undef RUN_FAIL
 #undef RUN_RC
+}
+
+
+// Many integrals of one family in one region list (see pg_batch.hip): each
+// live integral runs exactly the iteration of pg_integrate, with its own
+// tolerance, cap and state; they share every kernel launch. At most
+// min(B, capacity / cap, BATCH_MAX_SLOTS) integrals are live at once (each
+// may grow to `cap` regions); the others start as slots free up.
+int pg_integrate_batch(pg_context *ctx, int family, int dim, int B,
+                       const double *params, int n_params, const double *lo,
+                       const double *hi, const double *rel_tol,
+                       const double *abs_tol, const pg_options *opt,
+                       pg_result *out) {
+    if (!ctx) return PG_EINVAL;
+    ctx->err.clear();
+    if (B < 1 || !params || !rel_tol || !out || !lo || !hi)
+        return fail(ctx, PG_EINVAL, "bad batch arguments");
+    pg_options o;
+    if (opt) o = *opt;
+    else pg_default_options(&o);
+    const int d = dim;
+    std::vector<FParams> fp(B);
+    for (int b = 0; b < B; ++b) {
+        pg_integrand f{family, dim, params + (size_t)b * n_params, n_params};
+        int rc = make_params(ctx, &f, &fp[b]);
+        if (rc) return rc;
+        if (!(rel_tol[b] > 0.0) && !((abs_tol ? abs_tol[b] : o.abs_tol) > 0.0))
+            return fail(ctx, PG_EINVAL, "integral %d has no positive tolerance", b);
+    }
+    for (int k = 0; k < d; ++k)
+        if (!(lo[k] < hi[k]) || !std::isfinite(lo[k]) || !std::isfinite(hi[k]))
+            return fail(ctx, PG_EINVAL, "empty or infinite range on axis %d", k);
+    if (o.init_splits < 1 || o.max_iters < 1)
+        return fail(ctx, PG_EINVAL, "init_splits / max_iters < 1");
+    const int64_t cap = o.max_regions > 0 ? o.max_regions : ctx->cap;
+    if (cap > ctx->cap)
+        return fail(ctx, PG_ENOMEM, "max_regions %lld above the capacity %lld",
+                    (long long)cap, (long long)ctx->cap);
+    int64_t g_d = 1;
+    for (int k = 0; k < d; ++k) {
+        g_d *= o.init_splits;
+        if (g_d > cap)
+            return fail(ctx, PG_EINVAL, "initial grid above the cap");
+    }
+    const int K = (int)std::max<int64_t>(
+        1, std::min<int64_t>({(int64_t)B, ctx->cap / cap,
+                              (int64_t)BATCH_MAX_SLOTS}));
+    HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    const Rule R = make_rule(d);
+    const int64_t ld = ctx->cap;
+    double a[PG_DIM_MAX], width[PG_DIM_MAX];
+    for (int k = 0; k < d; ++k) {
+        a[k] = lo[k];
+        width[k] = (hi[k] - lo[k]) / (double)o.init_splits;
+    }
+
+    struct Slot {
+        int b = -1, it = 0;
+        double v_f = 0, e_f = 0, prev = NAN, v_tot = 0, e_tot = 0;
+        int64_t start = 0, n = 0, n_rel = 0;
+        int paired = 0;
+    };
+    std::vector<Slot> slots(K);
+    std::vector<int> order, free_slots;
+    for (int k = K - 1; k >= 0; --k) free_slots.push_back(k);
+    for (int b = 0; b < B; ++b) {
+        std::memset(&out[b], 0, sizeof(pg_result));
+        out[b].estimate = NAN;
+        out[b].error = NAN;
+    }
+    int next_b = 0;
+    int cur = 0;
+    // host copy of the slot table; every upload goes through one of two
+    // pinned staging halves in turn (between two uploads from the same half
+    // there is always a stream synchronisation)
+    std::vector<BInst> HIv(K);
+    BInst *HI = HIv.data();
+    int stage = 0;
+    std::vector<Totals> Tc(K);                  // classify totals per slot
+    auto finish = [&](int k, int status) {
+        Slot &S = slots[k];
+        pg_result &r = out[S.b];
+        r.estimate = S.v_tot;
+        r.error = S.e_tot;
+        r.status = status;
+        r.iterations = S.it;
+        r.fevals = r.regions_evaluated * npoints(d);
+        r.eval_launches = S.it;
+        HI[k].live = 0;
+    };
+    // admit integrals into free slots; their boxes go to [running, ...) of
+    // the list being built
+    int64_t running = 0;
+    int nnew = 0;
+    auto admit = [&]() {
+        nnew = 0;
+        while (next_b < B && !free_slots.empty()) {
+            const int k = free_slots.back();
+            free_slots.pop_back();
+            Slot &S = slots[k];
+            S = Slot{};
+            S.b = next_b++;
+            S.start = running;
+            S.n = g_d;
+            ctx->hb_table[k] = fp[S.b];
+            std::memset(&HI[k], 0, sizeof(BInst));
+            HI[k].out_start = running;
+            ctx->hb_new[nnew++] = k;
+            order.push_back(k);
+            running += g_d;
+        }
+    };
+    auto upload_inst = [&]() -> int {
+        BInst *h = ctx->hb_inst + (size_t)stage * BATCH_MAX_SLOTS;
+        stage = 1 - stage;
+        std::memcpy(h, HI, sizeof(BInst) * K);
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->b_inst, h, sizeof(BInst) * K,
+                                        hipMemcpyHostToDevice, st));
+        return PG_OK;
+    };
+#define BRUN(expr)                                                             \
+    do {                                                                       \
+        int rc_ = (expr);                                                      \
+        if (rc_) return rc_;                                                   \
+    } while (0)
+
+    admit();
+    if (nnew) {
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->b_table, ctx->hb_table,
+                                        sizeof(FParams) * K,
+                                        hipMemcpyHostToDevice, st));
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->b_new, ctx->hb_new,
+                                        sizeof(int32_t) * nnew,
+                                        hipMemcpyHostToDevice, st));
+        BRUN(upload_inst());
+        HIP_OR_FAIL(ctx, launch_batch_init(st, d, o.init_splits, a, width, nnew,
+                                           ctx->b_new, ctx->b_inst,
+                                           ctx->lo[cur], ctx->w[cur], ld,
+                                           ctx->inst[cur]));
+    }
+    int64_t n_total = running;
+    const FParams dummy{};
+    while (!order.empty()) {
+        // ---- per-slot layout of the current list
+        int64_t seg0 = 0, cls0 = 0;
+        for (size_t q = 0; q < order.size(); ++q) {
+            const int k = order[q];
+            Slot &S = slots[k];
+            ++S.it;
+            out[S.b].regions_evaluated += S.n;
+            out[S.b].peak_regions = std::max<int64_t>(out[S.b].peak_regions, S.n);
+            BInst &I = HI[k];
+            I.start = S.start;
+            I.n = S.n;
+            I.paired = S.paired;
+            I.tau = rel_tol[S.b];
+            I.relerr = o.relerr_filter;
+            I.live = 1;
+            I.searching = 0;
+            I.seg0 = seg0;
+            I.cls0 = cls0;
+            if (S.paired) {
+                const int64_t nh = (S.n / 2 + SEG - 1) / SEG;
+                I.nseg = 2 * nh;
+                I.ncls = nh;
+            } else {
+                I.nseg = (S.n + SEG - 1) / SEG;
+                I.ncls = I.nseg;
+            }
+            seg0 += I.nseg;
+            cls0 += I.ncls;
+            ctx->hb_order[q] = k;
+        }
+        const int nslots = (int)order.size();
+        const int64_t nseg = seg0, ncls = cls0;
+        if (nseg > ctx->nseg_max)
+            return fail(ctx, PG_ENOMEM, "segment table overflow");
+        BRUN(upload_inst());
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->b_order, ctx->hb_order,
+                                        sizeof(int32_t) * nslots,
+                                        hipMemcpyHostToDevice, st));
+        // ---- EVALUATE, TWO-LEVEL + CLASSIFY, per-slot sums
+        HIP_OR_FAIL(ctx, launch_evaluate(st, family, d, dummy, R, n_total,
+                                         ctx->lo[cur], ctx->w[cur], ld, ctx->V,
+                                         ctx->E, ctx->K, eval_waves(d, n_total),
+                                         ctx->inst[cur], ctx->b_table));
+        HIP_OR_FAIL(ctx, launch_batch_tables(st, nslots, ctx->b_order,
+                                             ctx->b_inst, ctx->b_segs,
+                                             ctx->b_cls));
+        HIP_OR_FAIL(ctx, launch_batch_classify(st, ncls, ctx->b_cls,
+                                               ctx->b_inst, ctx->V, ctx->E,
+                                               ctx->Vp, ctx->A, ctx->part));
+        HIP_OR_FAIL(ctx, launch_batch_reduce(st, nslots, ctx->b_order,
+                                             ctx->b_inst, ctx->part, ctx->off,
+                                             ctx->b_tot));
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->hb_tot, ctx->b_tot,
+                                        sizeof(Totals) * K,
+                                        hipMemcpyDeviceToHost, st));
+        HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
+        // ---- termination test and threshold triggers, per slot
+        int searching = 0;
+        for (int k : order) {
+            Slot &S = slots[k];
+            const Totals &T = ctx->hb_tot[k];
+            Tc[k] = T;
+            const double tau = rel_tol[S.b];
+            const double atol = abs_tol ? abs_tol[S.b] : o.abs_tol;
+            S.v_tot = T.v + S.v_f;
+            S.e_tot = T.e + S.e_f;
+            S.n_rel = (int64_t)T.cnt;
+            if (S.e_tot <= tau * std::fabs(S.v_tot) || S.e_tot <= atol) {
+                finish(k, PG_OK);
+                continue;
+            }
+            const bool trig_a = o.threshold_filter && S.it >= 2 &&
+                                std::fabs(S.v_tot - S.prev) <= tau * std::fabs(S.v_tot);
+            const bool trig_b = o.threshold_filter && 2 * S.n_rel > cap;
+            if (trig_a || trig_b) {
+                SearchState z{};
+                z.n = S.n;
+                z.e_it = T.e;
+                z.allowance = T.e - (S.e_tot - tau * std::fabs(S.v_tot));
+                z.mem = trig_b ? 1 : 0;
+                z.mn = T.emin;
+                z.mx = T.emax;
+                z.t = T.e / (double)S.n;
+                z.P_max = 0.25;
+                z.t_acc = -HUGE_VAL;
+                ctx->hb_state[k] = z;
+                HI[k].searching = 1;
+                ++out[S.b].threshold_calls;
+                ++searching;
+            }
+        }
+        BRUN(upload_inst());
+        // ---- THRESHOLD-CLASSIFY for every slot that needs it
+        if (searching) {
+            HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->b_state, ctx->hb_state,
+                                            sizeof(SearchState) * K,
+                                            hipMemcpyHostToDevice, st));
+            const int max_passes =
+                (THR_MAX_TRIALS + TRIAL_DEPTH - 1) / TRIAL_DEPTH;
+            int passes = 0;
+            for (int bi = 0; bi < 3 && passes < max_passes; ++bi) {
+                const int batch = std::min(SEARCH_BATCHES[bi], max_passes - passes);
+                for (int q = 0; q < batch; ++q)
+                    HIP_OR_FAIL(ctx, launch_batch_search_pass(
+                                         st, nseg, ctx->b_segs, nslots,
+                                         ctx->b_order, ctx->b_inst, ctx->E,
+                                         ctx->A, ctx->b_state, ctx->b_tpart));
+                passes += batch;
+                HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->hb_state, ctx->b_state,
+                                                sizeof(SearchState) * K,
+                                                hipMemcpyDeviceToHost, st));
+                HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
+                bool all = true;
+                for (int k : order)
+                    if (HI[k].searching && !ctx->hb_state[k].done) all = false;
+                if (all) break;
+            }
+            for (int k : order) {
+                if (!HI[k].searching) continue;
+                SearchState &z = ctx->hb_state[k];
+                if (!z.done) z.ok = 0;                 // trial limit reached
+                out[slots[k].b].threshold_trials += z.trials;
+            }
+            HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->b_state, ctx->hb_state,
+                                            sizeof(SearchState) * K,
+                                            hipMemcpyHostToDevice, st));
+        }
+        // ---- survivors per slot
+        HIP_OR_FAIL(ctx, launch_batch_count(st, nseg, ctx->b_segs, ctx->b_inst,
+                                            ctx->b_state, ctx->V, ctx->E,
+                                            ctx->A, ctx->part));
+        HIP_OR_FAIL(ctx, launch_batch_reduce(st, nslots, ctx->b_order,
+                                             ctx->b_inst, ctx->part, ctx->off,
+                                             ctx->b_tot));
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->hb_tot, ctx->b_tot,
+                                        sizeof(Totals) * K,
+                                        hipMemcpyDeviceToHost, st));
+        HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
+        running = 0;
+        std::vector<int> next_order;
+        for (int k : order) {
+            Slot &S = slots[k];
+            BInst &I = HI[k];
+            if (!I.live) {                             // converged above
+                free_slots.push_back(k);
+                continue;
+            }
+            const bool ok = I.searching && ctx->hb_state[k].ok;
+            int status = -1;
+            if (!ok && 2 * S.n_rel > cap) status = PG_MEMORY_EXHAUSTED;
+            const int64_t n_act = (int64_t)ctx->hb_tot[k].cnt;
+            if (status < 0 && n_act == 0) status = PG_NO_ACTIVE;
+            if (status < 0 && S.it == o.max_iters) status = PG_MAX_ITERS;
+            if (status >= 0) {
+                finish(k, status);
+                free_slots.push_back(k);
+                continue;
+            }
+            // finished contributions: this iteration's sums (v, e) less the
+            // survivors' (from the classify pass unless a threshold was
+            // accepted, as in pg_integrate)
+            const Totals &T = Tc[k];
+            const Totals &Ts = ok ? ctx->hb_tot[k] : T;
+            S.prev = S.v_tot;
+            S.v_f = T.v - Ts.av + S.v_f;
+            S.e_f = T.e - Ts.ae + S.e_f;
+            I.out_start = running;
+            I.na = n_act;
+            running += 2 * n_act;
+            S.start = I.out_start;
+            S.n = 2 * n_act;
+            S.paired = 1;
+            next_order.push_back(k);
+        }
+        order.swap(next_order);
+        admit();
+        BRUN(upload_inst());
+        HIP_OR_FAIL(ctx, launch_batch_compact(
+                             st, d, nseg, ctx->b_segs, ctx->b_inst,
+                             ctx->b_state, ctx->A, ctx->E, ctx->V, ctx->K,
+                             ctx->lo[cur], ctx->w[cur], ld, ctx->off,
+                             ctx->lo[1 - cur], ctx->w[1 - cur], ctx->Vp,
+                             ctx->inst[1 - cur]));
+        if (nnew) {
+            HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->b_table, ctx->hb_table,
+                                            sizeof(FParams) * K,
+                                            hipMemcpyHostToDevice, st));
+            HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->b_new, ctx->hb_new,
+                                            sizeof(int32_t) * nnew,
+                                            hipMemcpyHostToDevice, st));
+            HIP_OR_FAIL(ctx, launch_batch_init(st, d, o.init_splits, a, width,
+                                               nnew, ctx->b_new, ctx->b_inst,
+                                               ctx->lo[1 - cur], ctx->w[1 - cur],
+                                               ld, ctx->inst[1 - cur]));
+        }
+        cur = 1 - cur;
+        n_total = running;
+    }
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
+#undef BRUN
+    return PG_OK;
 }
 
 }  // extern "C"

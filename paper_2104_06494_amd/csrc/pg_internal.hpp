@@ -96,15 +96,86 @@ struct SearchState {
     int done, ok;
 };
 
-// ---- launchers (pg_kernels.hip); all queue on `st` -----------------------
+// ---- many integrals in one list (pg_batch.hip) ---------------------------
+// Each live integral of a batched run owns a slot. Its regions are
+// contiguous in the list; its survivors' children go to its own block of
+// the next list (lower halves, then upper halves), so sibling, parent and
+// segment arithmetic is the single-integral arithmetic shifted by `start`.
+constexpr int BATCH_MAX_SLOTS = 1024;
+
+struct BInst {
+    int64_t start, n;         // its regions in the current list
+    int64_t out_start, na;    // survivors; children at out_start + [0, 2 na)
+    int64_t seg0, nseg;       // its segments in the segment table
+    int64_t cls0, ncls;       // its classify items
+    double tau;               // rel_tol
+    int32_t relerr, paired;
+    int32_t live;             // 0: ends this iteration, nothing survives
+    int32_t searching;        // a threshold search runs this iteration
+};
+
+// A segment (no segment straddles an integral or the halves of a paired
+// integral) and a classify item (a segment, or for paired integrals a range
+// of sibling pairs feeding one lower and one upper segment).
+struct BSeg {
+    int64_t start, end;
+    uint32_t slot;
+    int32_t pad;
+};
+struct BCls {
+    int64_t q0, q1, s_lo, s_hi;
+    uint32_t slot;
+    int32_t pad;
+};
+
+hipError_t launch_batch_tables(hipStream_t st, int nslots, const int32_t *order,
+                               const BInst *inst, BSeg *segs, BCls *cls);
+hipError_t launch_batch_classify(hipStream_t st, int64_t ncls, const BCls *cls,
+                                 const BInst *inst, const double *V, double *E,
+                                 const double *Vp, uint8_t *A,
+                                 SegPartials part);
+hipError_t launch_batch_reduce(hipStream_t st, int nslots,
+                               const int32_t *order, const BInst *inst,
+                               SegPartials part, uint32_t *offsets,
+                               Totals *tot);
+hipError_t launch_batch_search_pass(hipStream_t st, int64_t nseg,
+                                    const BSeg *segs, int nslots,
+                                    const int32_t *order, const BInst *inst,
+                                    const double *E, const uint8_t *A_rel,
+                                    SearchState *states, double *tpart);
+hipError_t launch_batch_count(hipStream_t st, int64_t nseg, const BSeg *segs,
+                              const BInst *inst, const SearchState *states,
+                              const double *V, const double *E,
+                              const uint8_t *A_rel, SegPartials part);
+hipError_t launch_batch_compact(hipStream_t st, int d, int64_t nseg,
+                                const BSeg *segs, const BInst *inst,
+                                const SearchState *states,
+                                const uint8_t *A_rel, const double *E,
+                                const double *V, const uint8_t *K,
+                                const double *lo, const double *w, int64_t ld,
+                                const uint32_t *offsets, double *lo_out,
+                                double *w_out, double *Vp,
+                                uint32_t *inst_out);
+// Uniform-Split of `nnew` new integrals: slot new_slots[j] gets g^d boxes
+// at inst[slot].out_start of the next list, tagged with its slot.
+hipError_t launch_batch_init(hipStream_t st, int d, int g, const double *a,
+                             const double *width, int nnew,
+                             const int32_t *new_slots, const BInst *inst,
+                             double *lo, double *w, int64_t ld,
+                             uint32_t *inst_out);
+
+// ---- launchers (pg_evaluate.hip, pg_list.hip); all queue on `st` ---------
 hipError_t launch_init(hipStream_t st, int d, int g, const double *a,
                        const double *width, double *lo, double *w,
                        int64_t ld);
-// waves: waves per block (1..16), block covers 64 regions.
+// waves: waves per block (1..8), block covers 64 regions. With inst and
+// table, region i takes its parameters from table[inst[i]] (P is unused).
 hipError_t launch_evaluate(hipStream_t st, int family, int d,
                            const FParams &P, const Rule &R, int64_t n,
                            const double *lo, const double *w, int64_t ld,
-                           double *V, double *E, uint8_t *K, int waves);
+                           double *V, double *E, uint8_t *K, int waves,
+                           const uint32_t *inst = nullptr,
+                           const FParams *table = nullptr);
 bool evaluate_supported(int family, int d);
 hipError_t launch_fvalues(hipStream_t st, int family, int d, const FParams &P,
                           int64_t n, const double *x, int64_t ld, double *y);

@@ -1,0 +1,188 @@
+"""GPU parity of the batched solver (many integrals in one region list).
+
+Each integral of a batched run must take exactly the decisions of the same
+integral run alone (Algorithm 2 per integral): same status, iterations,
+regions, threshold calls; estimate and error equal up to the rounding of
+the threshold-search sums (which are added per segment in a batched run and
+per grid-stride block in a single run). The single run itself is certified
+against the oracle by trace replay elsewhere; here a few integrals are also
+compared with the oracle directly, and converged ones with closed forms.
+
+Each test prints the case it runs before touching the GPU.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from workloads import closed_forms as cf
+
+from parity import rel_close
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _ctx(capacity, d):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2104_06494_amd as pg
+    torch.cuda.set_device(0)
+    return pg.Context(capacity=capacity, dim_max=d)
+
+
+def _small_corner_batch(B, seed, lo_tol=-6.0, hi_tol=-3.0, cap=1 << 16):
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(0.0, 2.0, size=(B, 6))
+    tol = 10.0 ** rng.uniform(lo_tol, hi_tol, size=B)
+    return W.BatchWorkload("corner_peak_small", "corner_peak", 6, a, tol,
+                           np.full(B, 1e-20), init_splits=2, max_regions=cap)
+
+
+def _assert_same_run(rb, rp, b, rel=1e-12):
+    where = f"integral {b}: batched {rb} vs single {rp}"
+    assert rb.status == rp.status, where
+    assert rb.iterations == rp.iterations, where
+    assert rb.regions_evaluated == rp.regions_evaluated, where
+    assert rb.peak_regions == rp.peak_regions, where
+    assert rb.threshold_calls == rp.threshold_calls, where
+    assert rb.fevals == rp.fevals, where
+    assert rel_close(rb.estimate, rp.estimate, rel), where
+    assert rel_close(rb.error, rp.error, rel), where
+
+
+def _check_against_single(ctx, wl, results):
+    for b, rb in enumerate(results):
+        rp = ctx.integrate_workload(wl.instance(b))
+        _assert_same_run(rb, rp, b)
+
+
+def test_batch_equals_single_runs():
+    """16 integrals, all in flight at once."""
+    _say("batch-vs-single B=16")
+    wl = _small_corner_batch(16, seed=40)
+    ctx = _ctx(16 * wl.max_regions, wl.d)
+    res = ctx.integrate_batch_workload(wl)
+    _check_against_single(ctx, wl, res)
+    for b, r in enumerate(res):
+        if r.status_name == "OK":
+            exact = cf.exact(wl.family, wl.params[b], wl.d)
+            assert abs(r.estimate - exact) <= wl.rel_tol[b] * abs(exact) * 10, b
+    ctx.close()
+
+
+def test_batch_admits_integrals_as_slots_free():
+    """13 integrals with room for 4 in flight: slots are reused as integrals
+    finish, and results do not depend on the admission order."""
+    _say("batch-admission B=13 K=4")
+    wl = _small_corner_batch(13, seed=41, lo_tol=-6.5, hi_tol=-2.0)
+    ctx = _ctx(4 * wl.max_regions + 7, wl.d)
+    res = ctx.integrate_batch_workload(wl)
+    _check_against_single(ctx, wl, res)
+    ctx.close()
+
+
+def test_batch_threshold_and_memory_paths():
+    """A small cap makes the memory trigger fire (threshold search under
+    memory pressure, MEMORY_EXHAUSTED when it fails) and a small iteration
+    limit ends others with MAX_ITERS; all statuses equal the single runs'."""
+    _say("batch-statuses")
+    wl = _small_corner_batch(12, seed=42, lo_tol=-8.0, hi_tol=-5.0, cap=3000)
+    ctx = _ctx(12 * 3000, wl.d)
+    res = ctx.integrate_batch_workload(wl)
+    _check_against_single(ctx, wl, res)
+    names = {r.status_name for r in res}
+    assert "MEMORY_EXHAUSTED" in names or any(r.threshold_calls for r in res), names
+    wl.max_iters = 4
+    res = ctx.integrate_batch_workload(wl)
+    _check_against_single(ctx, wl, res)
+    assert any(r.status_name == "MAX_ITERS" for r in res)
+    ctx.close()
+
+
+@pytest.mark.parametrize("family,d,g", [("gaussian", 5, 3), ("product_peak", 3, 4),
+                                        ("oscillatory", 8, 2)])
+def test_batch_other_families(family, d, g):
+    """Odd initial grids (3^5 = 243 regions) and the other families."""
+    _say("batch-family", family, d, g)
+    B = 6
+    rng = np.random.default_rng(43 + d)
+    if family == "oscillatory":
+        P = np.concatenate([rng.uniform(0, 3, (B, d)), rng.uniform(0, 1, (B, 1))], 1)
+        tol, relerr = np.full(B, 1e-4), 0
+    else:
+        lo_a, hi_a = (10.0, 25.0) if family == "gaussian" else (2.0, 8.0)
+        P = np.concatenate([rng.uniform(lo_a, hi_a, (B, d)),
+                            rng.uniform(0.3, 0.7, (B, d))], 1)
+        tol, relerr = 10.0 ** rng.uniform(-6, -3, B), 1
+    wl = W.BatchWorkload(f"{family}_batch", family, d, P, tol, np.full(B, 1e-20),
+                         init_splits=g, max_regions=1 << 17, relerr_filter=relerr)
+    ctx = _ctx(B * wl.max_regions, d)
+    res = ctx.integrate_batch_workload(wl)
+    _check_against_single(ctx, wl, res)
+    ctx.close()
+
+
+def test_batch_against_oracle_directly():
+    """Four integrals compared with the oracle's own free run."""
+    _say("batch-vs-oracle")
+    wl = _small_corner_batch(4, seed=44, lo_tol=-5.0, hi_tol=-3.0)
+    ctx = _ctx(4 * wl.max_regions, wl.d)
+    res = ctx.integrate_batch_workload(wl)
+    for b, r in enumerate(res):
+        o = oracle.integrate_workload(wl.instance(b))
+        assert (r.status, r.iterations, r.regions_evaluated) == \
+            (o.status, o.iterations, o.regions_evaluated), (b, r, o)
+        assert rel_close(r.estimate, o.estimate, 1e-10), (b, r.estimate, o.estimate)
+        assert rel_close(r.error, o.error, 1e-10), (b, r.error, o.error)
+    ctx.close()
+
+
+def test_batch_headline_sample():
+    """The first 24 integrals of the 1024-integral d=6 corner-peak batch at
+    its full cap (2^21 regions each, 8 in flight), against single runs."""
+    _say("batch-headline-sample")
+    wl = W.corner_peak_batch_d6()
+    ctx = _ctx(8 * wl.max_regions, wl.d)
+    res = ctx.integrate_batch_workload(wl, count=24)
+    _check_against_single(ctx, wl, res)
+    for b, r in enumerate(res):
+        assert r.status_name == "OK", (b, r)
+        exact = cf.exact(wl.family, wl.params[b], wl.d)
+        assert abs(r.estimate - exact) <= wl.rel_tol[b] * abs(exact) * 10, b
+    ctx.close()
+
+
+def test_batch_bitwise_reproducible():
+    _say("batch-determinism")
+    wl = _small_corner_batch(8, seed=45)
+    ctx = _ctx(8 * wl.max_regions, wl.d)
+    r1 = ctx.integrate_batch_workload(wl)
+    r2 = ctx.integrate_batch_workload(wl)
+    assert [(r.estimate, r.error, r.regions_evaluated) for r in r1] == \
+        [(r.estimate, r.error, r.regions_evaluated) for r in r2]
+    ctx.close()
+
+
+def test_batch_invalid_arguments():
+    _say("batch-invalid")
+    import paper_2104_06494_amd as pg
+    ctx = _ctx(1 << 16, 6)
+    P = np.ones((3, 6))
+    with pytest.raises(pg.PaganiError):
+        ctx.integrate_batch("corner_peak", 6, P, rel_tol=[1e-3, 0.0, 1e-3], abs_tol=0.0)
+    with pytest.raises(pg.PaganiError):
+        ctx.integrate_batch("corner_peak", 6, np.ones((3, 5)), rel_tol=1e-3)
+    with pytest.raises(pg.PaganiError):
+        ctx.integrate_batch("corner_peak", 6, P, rel_tol=1e-3, max_regions=1 << 17)
+    with pytest.raises(pg.PaganiError):
+        ctx.integrate_batch("corner_peak", 6, P, rel_tol=1e-3, init_splits=7)
+    ctx.close()

@@ -156,6 +156,36 @@ class BatchWorkload:
     rel_tol: np.ndarray      # [B]
     abs_tol: np.ndarray      # [B]
     init_splits: int = 2
+    max_regions: int = 1 << 21   # cap of each integral's live list
+    max_iters: int = 100
+    relerr_filter: int = 1
+    threshold_filter: int = 1
+    lo: np.ndarray = field(default=None)
+    hi: np.ndarray = field(default=None)
+
+    def __post_init__(self):
+        if self.lo is None:
+            self.lo = np.zeros(self.d)
+        if self.hi is None:
+            self.hi = np.ones(self.d)
+
+    @property
+    def B(self) -> int:
+        return int(self.params.shape[0])
+
+    @property
+    def npoints(self) -> int:
+        return (1 << self.d) + 2 * self.d * self.d + 2 * self.d + 1
+
+    def instance(self, b: int) -> "Workload":
+        """Integral b as a single workload (same options)."""
+        return Workload(f"{self.name}[{b}]", self.family, self.d,
+                        np.array(self.params[b]), float(self.rel_tol[b]),
+                        init_splits=self.init_splits, max_regions=self.max_regions,
+                        max_iters=self.max_iters, abs_tol=float(self.abs_tol[b]),
+                        relerr_filter=self.relerr_filter,
+                        threshold_filter=self.threshold_filter,
+                        lo=self.lo, hi=self.hi)
 
 
 def corner_peak_batch_d6(B: int = 1024, seed: int = 4) -> BatchWorkload:
