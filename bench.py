@@ -38,7 +38,7 @@ F_GAUSSIAN_D5 = 47.0
 # HBM bytes per evaluate launch of this workload from FETCH_SIZE / WRITE_SIZE
 # (scaled by a plain copy), valid only for the kernel source they were taken
 # on (first 16 hex digits of its sha256); reported as null otherwise.
-EVAL_TRAFFIC = {"bytes_per_launch": 37555060.0, "kernel_sha256": "7bdd3c4a3d3760c5",
+EVAL_TRAFFIC = {"bytes_per_launch": 37569203.0, "kernel_sha256": "c18f8b134e26a73c",
                 "profile": "profiles/evaluate_gaussian_d5_counters.txt"}
 # MI355X FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz.
 PEAK_FP64_TFLOPS = 78.6
@@ -143,35 +143,43 @@ def batched(args):
     from workloads import closed_forms as cf
 
     wl = W.corner_peak_batch_d6()
+    B = min(wl.B, args.batch_count) if args.batch_count else wl.B
     slots = args.batch_slots
     ctx = pg.Context(capacity=slots * wl.max_regions, dim_max=wl.d)
-    ctx.integrate_batch_workload(wl, count=min(wl.B, 2 * slots))
+    ctx.integrate_batch_workload(wl, count=min(B, 2 * slots))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    rb = ctx.integrate_batch_workload(wl)
+    rb = ctx.integrate_batch_workload(wl, count=B)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    rp = [ctx.integrate_workload(wl.instance(b)) for b in range(wl.B)]
-    torch.cuda.synchronize()
-    tp = time.perf_counter() - t0
     fe = sum(r.fevals for r in rb)
-    same = sum((a.status, a.iterations, a.regions_evaluated) ==
-               (b.status, b.iterations, b.regions_evaluated) for a, b in zip(rb, rp))
     met = 0
     for b, r in enumerate(rb):
         exact = cf.exact(wl.family, wl.params[b], wl.d)
         met += abs(r.estimate - exact) <= wl.rel_tol[b] * abs(exact)
+    out = {"workload": "corner_peak_batch_d6", "B": B, "slots_in_flight": slots,
+           "evals_per_s": fe / tb, "wall_ms": 1e3 * tb, "fevals": fe,
+           "status_ok": sum(r.status_name == "OK" for r in rb),
+           "closed_form_met": int(met),
+           "regions_evaluated": sum(r.regions_evaluated for r in rb),
+           "max_iterations": max(r.iterations for r in rb)}
+    if not args.no_plain:
+        t0 = time.perf_counter()
+        rp = [ctx.integrate_workload(wl.instance(b)) for b in range(B)]
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        out["plain_sequential"] = {"evals_per_s": fe / tp, "wall_ms": 1e3 * tp}
+        out["speedup_vs_plain"] = tp / tb
+        out["same_schedule_as_plain"] = sum(
+            (a.status, a.iterations, a.regions_evaluated) ==
+            (b.status, b.iterations, b.regions_evaluated) for a, b in zip(rb, rp))
     ctx.close()
-    return {"workload": "corner_peak_batch_d6", "B": wl.B, "slots_in_flight": slots,
-            "evals_per_s": fe / tb, "wall_ms": 1e3 * tb,
-            "plain_sequential": {"evals_per_s": fe / tp, "wall_ms": 1e3 * tp},
-            "speedup_vs_plain": tp / tb, "fevals": fe,
-            "same_schedule_as_plain": same,
-            "status_ok": sum(r.status_name == "OK" for r in rb),
-            "closed_form_met": int(met),
-            "regions_evaluated": sum(r.regions_evaluated for r in rb),
-            "max_iterations": max(r.iterations for r in rb)}
+    return out
+
+
+def batched_mode(args):
+    """The batched comparison alone (for profiling)."""
+    print(json.dumps({"mode": "batched", **batched(args)}), flush=True)
 
 
 def cpu_baseline(wl):
@@ -224,10 +232,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", choices=["headline", "integrand", "copy"], default="headline")
+    ap.add_argument("--mode", choices=["headline", "batched", "integrand", "copy"],
+                    default="headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-vs-plain comparison")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="batched run without the single-run comparison")
+    ap.add_argument("--batch-count", type=int, default=0,
+                    help="first integrals of the batch only (0 = all 1024)")
     ap.add_argument("--batch-slots", type=int, default=64,
                     help="integrals in flight in the batched run (each "
                          "reserves 2^21 regions of workspace)")
@@ -237,7 +250,8 @@ def main():
               "supported (the method's multi-GPU sharding is a design note, not code)",
               file=sys.stderr)
         sys.exit(2)
-    {"headline": headline, "integrand": integrand_mode, "copy": copy_mode}[args.mode](args)
+    {"headline": headline, "batched": batched_mode, "integrand": integrand_mode,
+     "copy": copy_mode}[args.mode](args)
 
 
 if __name__ == "__main__":
