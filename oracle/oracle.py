@@ -79,7 +79,13 @@ def lib():
                                    C.c_double, C.c_int, C.c_int, C.c_int,
                                    C.c_int, C.c_int64, C.c_char_p, _dp,
                                    np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS"),
-                                   C.POINTER(ReplayStats)]
+                                   C.POINTER(ReplayStats), C.c_void_p, C.c_void_p,
+                                   C.c_void_p]
+    L.oracle_grad_f.restype = C.c_int
+    L.oracle_grad_f.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp]
+    L.oracle_grad_regions.restype = C.c_int
+    L.oracle_grad_regions.argtypes = [C.c_int, C.c_int, _dp, C.c_long, _dp, _dp,
+                                      C.c_long, _dp, _dp]
     _lib = L
     return L
 
@@ -212,6 +218,9 @@ class OracleResult:
     eval_seconds: float
     seconds: float
     replay: dict | None = None
+    grad: np.ndarray | None = None       # d estimate / d params over the leaves
+    grad_abs: np.ndarray | None = None   # sum of the absolute terms of grad
+    leaf_v: float | None = None          # sum of the leaves' estimates
 
     @property
     def status_name(self):
@@ -221,24 +230,57 @@ class OracleResult:
 def integrate(family: str, d: int, params, lo=None, hi=None, rel_tol=1e-3,
               abs_tol=1e-20, init_splits=4, max_iters=100, relerr_filter=1,
               threshold_filter=1, max_regions=1 << 22,
-              replay_path: str | None = None) -> OracleResult:
-    """PAGANI main loop (Algorithm 2), free mode or replaying a GPU trace."""
+              replay_path: str | None = None, grad: bool = False) -> OracleResult:
+    """PAGANI main loop (Algorithm 2), free mode or replaying a GPU trace.
+    With grad=True also the derivative of the estimate with respect to the
+    parameters over the partition the run ends on (its leaves: every region
+    finished on the way and the live list at the end)."""
     lo = np.zeros(d) if lo is None else _f64(lo)
     hi = np.ones(d) if hi is None else _f64(hi)
     out_d = np.zeros(4)
     out_i = np.zeros(7, np.int64)
     rs = ReplayStats()
+    npar = len(np.atleast_1d(params))
+    g = np.zeros(npar) if grad else None
+    ga = np.zeros(npar) if grad else None
+    lv = np.zeros(1)
     rc = lib().oracle_integrate(FAMILY_ID[family], d, _f64(params), lo, hi,
                                 rel_tol, abs_tol, init_splits, max_iters,
                                 relerr_filter, threshold_filter, max_regions,
                                 replay_path.encode() if replay_path else None,
-                                out_d, out_i, C.byref(rs))
+                                out_d, out_i, C.byref(rs), _ptr(g), _ptr(ga), _ptr(lv))
     if rc:
         raise RuntimeError(f"oracle_integrate failed with code {rc}")
     return OracleResult(out_d[0], out_d[1], int(out_i[0]), int(out_i[1]),
                         int(out_i[2]), int(out_i[3]), int(out_i[4]),
                         int(out_i[5]), int(out_i[6]), out_d[2], out_d[3],
-                        rs.as_dict() if replay_path else None)
+                        rs.as_dict() if replay_path else None, g, ga, float(lv[0]))
+
+
+def grad_f(family: str, params, x) -> np.ndarray:
+    """Partial derivatives of one integrand value with respect to its
+    parameters (same layout as params)."""
+    x = _f64(x)
+    p = _f64(params)
+    df = np.zeros(2 * len(x) + 2)
+    n = lib().oracle_grad_f(FAMILY_ID[family], len(x), p, x, df)
+    if n < 0:
+        raise ValueError(f"no parameter gradient for {family}")
+    return df[:n]
+
+
+def grad_regions(family: str, d: int, params, lo, w):
+    """Derivative of the summed degree-7 estimates of the regions (SoA
+    [d, n] corners and widths) with respect to the parameters, and the sum
+    of the absolute terms (the adjoint over a fixed partition)."""
+    lo, w = _f64(lo), _f64(w)
+    n = lo.shape[1]
+    G = np.zeros(2 * d + 2)
+    Ga = np.zeros(2 * d + 2)
+    k = lib().oracle_grad_regions(FAMILY_ID[family], d, _f64(params), n, lo, w, n, G, Ga)
+    if k < 0:
+        raise ValueError(f"no parameter gradient for {family}")
+    return G[:k], Ga[:k]
 
 
 def integrate_workload(wl, **kw) -> OracleResult:
@@ -255,4 +297,5 @@ def integrate_workload(wl, **kw) -> OracleResult:
 __all__ = ["lib", "npoints", "rule", "f", "eval_regions", "two_level",
            "classify", "csum", "threshold_search", "filter_split",
            "uniform_split", "integrate", "integrate_workload", "OracleResult",
+           "grad_f", "grad_regions",
            "RegionEval", "FAMILY_ID", "STATUS"]

@@ -286,6 +286,193 @@ int oracle_eval_regions(int family, int d, const double *par, long n,
 }
 
 /* ------------------------------------------------------------------------
+ * Parameter derivatives of the integrands. Over a fixed set of regions the
+ * estimate is a sum of rule values, each a weighted sum of f at points that
+ * do not depend on the parameters, so its derivative with respect to a
+ * parameter is the same weighted sum of the partial derivative of f (the
+ * adjoint of the estimate over the partition the run converged on).
+ * df receives one value per parameter, in the layout of oracle_f. Returns
+ * the number of parameters, or -1 for the monomial family (its exponents
+ * are integers) and unknown families.
+ * ---------------------------------------------------------------------- */
+int oracle_grad_f(int family, int d, const double *p, const double *x,
+                  double *df)
+{
+    int i;
+    double f, s, t, q, a;
+    switch (family) {
+    case OR_PRODUCT_PEAK:
+        /* f = prod_i 1 / q_i with q_i = a_i^-2 + t_i^2, t_i = x_i - u_i:
+           d/da_i = f (2 / a_i^3) / q_i,  d/du_i = f (2 t_i) / q_i */
+        f = oracle_f(family, d, p, x);
+        for (i = 0; i < d; i++) {
+            a = p[i];
+            t = x[i] - p[d + i];
+            q = 1.0 / (a * a) + t * t;
+            df[i] = f * (2.0 / (a * a * a)) / q;
+            df[d + i] = f * (2.0 * t) / q;
+        }
+        return 2 * d;
+    case OR_GAUSSIAN:
+        /* f = exp(-sum_i a_i^2 t_i^2):
+           d/da_i = -2 a_i t_i^2 f,  d/du_i = 2 a_i^2 t_i f */
+        f = oracle_f(family, d, p, x);
+        for (i = 0; i < d; i++) {
+            a = p[i];
+            t = x[i] - p[d + i];
+            df[i] = -2.0 * a * (t * t) * f;
+            df[d + i] = 2.0 * (a * a) * t * f;
+        }
+        return 2 * d;
+    case OR_OSCILLATORY:
+        /* f = cos(phi), phi = 2 pi u_1 + sum_i a_i x_i:
+           d/da_i = -x_i sin(phi),  d/du_1 = -2 pi sin(phi) */
+        s = 2.0 * M_PI * p[d];
+        for (i = 0; i < d; i++)
+            s = s + p[i] * x[i];
+        f = sin(s);
+        for (i = 0; i < d; i++)
+            df[i] = -x[i] * f;
+        df[d] = -2.0 * M_PI * f;
+        return d + 1;
+    case OR_CORNER_PEAK:
+        /* f = s^-(d+1), s = 1 + sum_i a_i x_i:
+           d/da_i = -(d+1) x_i s^-(d+2) */
+        s = 1.0;
+        for (i = 0; i < d; i++)
+            s = s + p[i] * x[i];
+        f = pow(s, -(double)(d + 2));
+        for (i = 0; i < d; i++)
+            df[i] = -(double)(d + 1) * x[i] * f;
+        return d;
+    default:
+        return -1;
+    }
+}
+
+/* Add w * df(x) to g and |w * df(x)| to gabs (np parameters). */
+static void grad_point(int family, int d, const double *par, const double *x,
+                       double wgt, int np, double *g, double *gabs)
+{
+    double df[2 * OR_DMAX + 2];
+    int q;
+    oracle_grad_f(family, d, par, x, df);
+    for (q = 0; q < np; q++) {
+        g[q] = g[q] + wgt * df[q];
+        gabs[q] = gabs[q] + fabs(wgt * df[q]);
+    }
+}
+
+/* Derivative of one region's degree-7 estimate: g[q] = vol sum_p w7(p)
+   df_q(x_p) over the points of reading R1, and gabs[q] the same sum of
+   absolute terms (the scale of its rounding). */
+static void grad_region(int family, int d, const double *par,
+                        const double *lo, const double *w, const double w7[5],
+                        const double lam[5], int np, double *g, double *gabs)
+{
+    double c[OR_DMAX], h[OR_DMAX], x[OR_DMAX], vol = 1.0;
+    int i, j, k, q, si, sj;
+    long b;
+    for (q = 0; q < np; q++) { g[q] = 0.0; gabs[q] = 0.0; }
+    for (i = 0; i < d; i++) {
+        h[i] = w[i] * 0.5;
+        c[i] = lo[i] + h[i];
+        vol = vol * w[i];
+    }
+    for (k = 0; k < d; k++) x[k] = c[k];
+    grad_point(family, d, par, x, w7[0], np, g, gabs);
+    for (i = 0; i < d; i++) {
+        int o;
+        for (o = 1; o <= 2; o++)
+            for (si = 0; si < 2; si++) {
+                for (k = 0; k < d; k++) x[k] = c[k];
+                x[i] = c[i] + (si == 0 ? 1.0 : -1.0) * (lam[o] * h[i]);
+                grad_point(family, d, par, x, w7[o], np, g, gabs);
+            }
+    }
+    for (i = 0; i < d; i++)
+        for (j = i + 1; j < d; j++)
+            for (si = 0; si < 2; si++)
+                for (sj = 0; sj < 2; sj++) {
+                    for (k = 0; k < d; k++) x[k] = c[k];
+                    x[i] = c[i] + (si == 0 ? 1.0 : -1.0) * (lam[3] * h[i]);
+                    x[j] = c[j] + (sj == 0 ? 1.0 : -1.0) * (lam[3] * h[j]);
+                    grad_point(family, d, par, x, w7[3], np, g, gabs);
+                }
+    for (b = 0; b < (1L << d); b++) {
+        for (k = 0; k < d; k++)
+            x[k] = c[k] + (((b >> k) & 1) ? -1.0 : 1.0) * (lam[4] * h[k]);
+        grad_point(family, d, par, x, w7[4], np, g, gabs);
+    }
+    for (q = 0; q < np; q++) {
+        g[q] = vol * g[q];
+        gabs[q] = vol * gabs[q];
+    }
+}
+
+/* Neumaier accumulator, one per parameter. */
+typedef struct { double s, c; } or_acc;
+
+static void acc_add(or_acc *a, double x)
+{
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x)) a->c = a->c + ((a->s - t) + x);
+    else a->c = a->c + ((x - t) + a->s);
+    a->s = t;
+}
+
+/* Add the estimate derivative of regions i in [0, n) of an SoA list (stride
+   ld) to G / Gabs, skipping i with mask[i] != 0 when a mask is given. */
+static void grad_list(int family, int d, const double *par, long n,
+                      const double *lo, const double *w, long ld,
+                      const uint8_t *skip, const double w7[5],
+                      const double lam[5], int np, or_acc *G, or_acc *Gabs)
+{
+    double l[OR_DMAX], ww[OR_DMAX], g[2 * OR_DMAX + 2], ga[2 * OR_DMAX + 2];
+    long i;
+    int k, q;
+    for (i = 0; i < n; i++) {
+        if (skip && skip[i]) continue;
+        for (k = 0; k < d; k++) {
+            l[k] = lo[k * ld + i];
+            ww[k] = w[k * ld + i];
+        }
+        grad_region(family, d, par, l, ww, w7, lam, np, g, ga);
+        for (q = 0; q < np; q++) {
+            acc_add(&G[q], g[q]);
+            acc_add(&Gabs[q], ga[q]);
+        }
+    }
+}
+
+/*
+ * Derivative of the sum of the degree-7 estimates of n regions (SoA lower
+ * corners and widths, stride ld) with respect to every parameter: G[np],
+ * and Gabs[np] the sum of the absolute terms. Returns np, or -1 when the
+ * family has no gradient.
+ */
+int oracle_grad_regions(int family, int d, const double *par, long n,
+                        const double *lo, const double *w, long ld,
+                        double *G, double *Gabs)
+{
+    double w7[5], w5[5], lam[5], df[2 * OR_DMAX + 2], x[OR_DMAX] = {0};
+    or_acc Ga[2 * OR_DMAX + 2], Gb[2 * OR_DMAX + 2];
+    int q, np;
+    if (d < 1 || d > OR_DMAX) return -1;
+    np = oracle_grad_f(family, d, par, x, df);
+    if (np < 0) return -1;
+    oracle_rule(d, w7, w5, lam);
+    memset(Ga, 0, sizeof Ga);
+    memset(Gb, 0, sizeof Gb);
+    grad_list(family, d, par, n, lo, w, ld, NULL, w7, lam, np, Ga, Gb);
+    for (q = 0; q < np; q++) {
+        G[q] = Ga[q].s + Ga[q].c;
+        Gabs[q] = Gb[q].s + Gb[q].c;
+    }
+    return np;
+}
+
+/* ------------------------------------------------------------------------
  * TWO-LEVEL-ERROR (Section 3.2, reading R4). The list holds 2*npairs
  * regions; region i and region i + npairs are the two halves of the parent
  * whose estimate is Vp[i]. E is refined in place.
@@ -514,12 +701,26 @@ static double now_s(void)
     return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
 }
 
+/* Every region of the current list (mask NULL) or those with mask[i] == 0
+   becomes a leaf of the final partition. */
+#define LEAVES(mask)                                                        \
+    do {                                                                    \
+        const uint8_t *m_ = (mask);                                         \
+        if (grad)                                                           \
+            grad_list(family, d, par, s, lo, w, s, m_, w7, lam, np, G,      \
+                      Gabs);                                                \
+        if (leaf_v)                                                         \
+            for (i = 0; i < s; i++)                                         \
+                if (!m_ || !m_[i]) acc_add(&LV, V[i]);                      \
+    } while (0)
+
 int oracle_integrate(int family, int d, const double *par,
                      const double *a, const double *b,
                      double tau_rel, double tau_abs, int g, int it_max,
                      int relerr_filter, int threshold_filter,
                      int64_t max_regions, const char *replay_path,
-                     double *out_d, int64_t *out_i, or_replay_stats *rs)
+                     double *out_d, int64_t *out_i, or_replay_stats *rs,
+                     double *grad, double *grad_abs, double *leaf_v)
 {
     double w7[5], w5[5], lam[5];
     double *lo = NULL, *w = NULL, *lo2 = NULL, *w2 = NULL;
@@ -534,6 +735,10 @@ int oracle_integrate(int family, int d, const double *par,
     int k, rc = OR_OK, verbose;
     FILE *tr = NULL;
     or_rec rec;
+    /* leaves of the partition (regions finished, and the live list when
+       the run ends): their estimate derivative and their estimates */
+    or_acc G[2 * OR_DMAX + 2], Gabs[2 * OR_DMAX + 2], LV = {0.0, 0.0};
+    int np = 0;
 
     if (d < 1 || d > OR_DMAX || g < 1 || it_max < 1) return OR_EINVAL;
     if (!(tau_rel > 0.0) && !(tau_abs > 0.0)) return OR_EINVAL;
@@ -580,6 +785,16 @@ int oracle_integrate(int family, int d, const double *par,
         goto done;
     }
     oracle_rule(d, w7, w5, lam);
+    memset(G, 0, sizeof G);
+    memset(Gabs, 0, sizeof Gabs);
+    if (grad) {
+        double df[2 * OR_DMAX + 2], x0[OR_DMAX] = {0};
+        np = oracle_grad_f(family, d, par, x0, df);
+        if (np < 0) {
+            rc = OR_EINVAL;
+            goto done;
+        }
+    }
     verbose = getenv("PAGANI_ORACLE_VERBOSE") != NULL;
     t0 = now_s();
 
@@ -665,6 +880,7 @@ int oracle_integrate(int family, int d, const double *par,
         }
         if (terminated) {
             status = OR_OK;
+            LEAVES(NULL);
             break;
         }
 
@@ -702,11 +918,13 @@ int oracle_integrate(int family, int d, const double *par,
             }
             if (!ok && 2 * n_rel > cap) {
                 status = OR_MEMORY_EXHAUSTED;
+                LEAVES(NULL);
                 break;
             }
             if (!ok) memcpy(A, A_rel, s);
         } else if (2 * n_rel > cap) {
             status = OR_MEMORY_EXHAUSTED;
+            LEAVES(NULL);
             break;
         }
 
@@ -740,12 +958,15 @@ int oracle_integrate(int family, int d, const double *par,
                     (long)n_act, v, e, v_f, e_f, invoke, ok, t, trials);
         if (n_act == 0) {
             status = OR_NO_ACTIVE;
+            LEAVES(NULL);
             break;
         }
         if (it == it_max) {
             status = OR_MAX_ITERS;
+            LEAVES(NULL);
             break;
         }
+        LEAVES(A);             /* the regions finished in this iteration */
 
         /* finished contributions v_f, e_f */
         v_f = v - oracle_sum(s, V, A) + v_f;
@@ -775,6 +996,11 @@ int oracle_integrate(int family, int d, const double *par,
     out_i[4] = peak;
     out_i[5] = thr_calls;
     out_i[6] = thr_trials;
+    for (k = 0; k < np; k++) {
+        grad[k] = G[k].s + G[k].c;
+        if (grad_abs) grad_abs[k] = Gabs[k].s + Gabs[k].c;
+    }
+    if (leaf_v) *leaf_v = LV.s + LV.c;
 
 done:
     if (tr) fclose(tr);

@@ -39,9 +39,34 @@ MUTANTS = {
 }
 
 
-@pytest.mark.parametrize("name", sorted(MUTANTS))
-def test_mutant_is_caught(name, tmp_path):
-    old, new = MUTANTS[name]
+# mistakes in the parameter derivatives and the leaf bookkeeping, caught by
+# the gradient pins
+GRAD_MUTANTS = {
+    "grad_gauss_u_sign": ("df[d + i] = 2.0 * (a * a) * t * f;",
+                          "df[d + i] = -2.0 * (a * a) * t * f;"),
+    "grad_gauss_a_factor": ("df[i] = -2.0 * a * (t * t) * f;",
+                            "df[i] = -1.0 * a * (t * t) * f;"),
+    "grad_product_peak_u": ("df[d + i] = f * (2.0 * t) / q;",
+                            "df[d + i] = f * (2.0 * t) * q;"),
+    "grad_osc_phase": ("df[d] = -2.0 * M_PI * f;", "df[d] = -M_PI * f;"),
+    "grad_corner_power": ("f = pow(s, -(double)(d + 2));",
+                          "f = pow(s, -(double)(d + 1));"),
+    "grad_orbit4_weight": ("grad_point(family, d, par, x, w7[3], np, g, gabs);",
+                           "grad_point(family, d, par, x, w7[2], np, g, gabs);"),
+    "grad_no_volume": ("        g[q] = vol * g[q];", "        g[q] = g[q];"),
+    "leaves_mask_inverted": ("if (skip && skip[i]) continue;",
+                             "if (skip && !skip[i]) continue;"),
+    "leaves_finished_dropped": ("        LEAVES(A);             /* the regions finished in this iteration */",
+                                "        /* finished regions dropped */"),
+}
+
+CASES = [(n, "test_oracle_pins.py") for n in sorted(MUTANTS)] + \
+        [(n, "test_oracle_grad_pins.py") for n in sorted(GRAD_MUTANTS)]
+
+
+@pytest.mark.parametrize("name,pins", CASES, ids=[c[0] for c in CASES])
+def test_mutant_is_caught(name, pins, tmp_path):
+    old, new = {**MUTANTS, **GRAD_MUTANTS}[name]
     src = open(SRC).read()
     assert src.count(old) == 1, f"mutation anchor not unique: {name}"
     mut = tmp_path / "mutant.c"
@@ -51,6 +76,6 @@ def test_mutant_is_caught(name, tmp_path):
                     "-shared", "-fPIC", "-o", str(lib), str(mut), "-lm"], check=True)
     env = dict(os.environ, PAGANI_ORACLE_LIB=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        "-m", "not slow", os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        "-m", "not slow", os.path.join(ROOT, "tests", pins)],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"

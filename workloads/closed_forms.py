@@ -77,6 +77,29 @@ def corner_peak(params, d) -> float:
     return float(total / den)
 
 
+def corner_peak_grad(params, d):
+    """Unit cube: dI/da_j of the corner-peak closed form, differentiated term
+    by term: with P = d! prod a_i and T = sum_S (-1)^|S| / (1 + sum_S a),
+    dI/da_j = -I / a_j - (1/P) sum_{S containing j} (-1)^|S| / (1 + sum_S a)^2.
+    Exact rational arithmetic over the double-precision a_i."""
+    a = [Fraction(float(x)) for x in params[:d]]
+    if any(x == 0 for x in a):
+        raise ValueError("corner_peak closed form needs every a_i != 0")
+    P = Fraction(factorial(d))
+    for x in a:
+        P *= x
+    T = Fraction(0)
+    dT = [Fraction(0)] * d
+    for k in range(d + 1):
+        for S in combinations(range(d), k):
+            den = 1 + sum((a[i] for i in S), Fraction(0))
+            T += Fraction((-1) ** k) / den
+            for j in S:
+                dT[j] -= Fraction((-1) ** k) / (den * den)
+    I = T / P
+    return np.array([float(-I / a[j] + dT[j] / P) for j in range(d)])
+
+
 def monomial(alpha, lo, hi) -> Fraction:
     """Exact prod_i (hi_i^(k+1) - lo_i^(k+1)) / (k+1) over a box with float corners."""
     r = Fraction(1)
