@@ -19,8 +19,10 @@ MUTANTS = {
                           "lambda[1] = sqrt(9.0 / 71.0);"),
     "dropped_orbit5": ("    for (k = 0; k < 5; k++) {\n        sum7",
                        "    for (k = 0; k < 4; k++) {\n        sum7"),
-    "orbit4_wrong_index": ("x[j] = c[j] + (sj == 0 ? 1.0 : -1.0) * (lam[3] * h[j]);",
-                           "x[j] = c[j] + (sj == 0 ? 1.0 : -1.0) * (lam[3] * h[i]);"),
+    "orbit4_wrong_index": ("x[j] = c[j] + (sj == 0 ? 1.0 : -1.0) * (lam[3] * h[j]);\n"
+                           "                    f = oracle_f(",
+                           "x[j] = c[j] + (sj == 0 ? 1.0 : -1.0) * (lam[3] * h[i]);\n"
+                           "                    f = oracle_f("),
     "fourth_diff_ratio": ("- (P3[i] - 2.0 * fc) / 7.0);", "- (P3[i] - 2.0 * fc) / 5.0);"),
     "two_level_transposed": ("E[b] = E[b] * g + delta;", "E[b] = E[a] * g + delta;"),
     "two_level_quarter": ("double delta = fabs(V[a] + V[b] - Vp[i]) / 4.0;",
