@@ -126,6 +126,8 @@ def headline(args):
     }
     if not args.no_batched:
         out["batched"] = batched(args)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)
@@ -174,7 +176,74 @@ def batched(args):
             (a.status, a.iterations, a.regions_evaluated) ==
             (b.status, b.iterations, b.regions_evaluated) for a, b in zip(rb, rp))
     ctx.close()
+    torch.cuda.empty_cache()
     return out
+
+
+def adjoint(args):
+    """The 256 d=6 Gaussian parameter points (a ~ U[5,20]^6, u ~ U[0.2,0.8]^6,
+    seed 5, rel_tol 1e-5, 2^6 initial grid, 2^22-region cap each), batched:
+    forward only, then forward plus the derivative over each final
+    partition (same decisions, so the same regions); and the forward as 256
+    single runs. Also how many estimates and gradients meet the closed form."""
+    import numpy as np
+    import torch
+    import paper_2104_06494_amd as pg
+    import workloads as W
+    from workloads import closed_forms as cf
+
+    wl = W.gaussian_grad_d6()
+    B = min(wl.B, args.batch_count) if args.batch_count else wl.B
+    slots = max(1, args.batch_slots // 2)
+    ctx = pg.Context(capacity=slots * wl.max_regions, dim_max=wl.d)
+    ctx.integrate_batch_workload(wl, count=min(B, slots), grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rf = ctx.integrate_batch_workload(wl, count=B)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rg, G, _ = ctx.integrate_batch_workload(wl, count=B, grad=True)
+    torch.cuda.synchronize()
+    tg = time.perf_counter() - t0
+    fe = sum(r.fevals for r in rf)
+    same = sum((a.status, a.regions_evaluated, a.estimate) ==
+               (b.status, b.regions_evaluated, b.estimate) for a, b in zip(rf, rg))
+    est_ok = grad_ok = 0
+    gerr = []
+    for b in range(B):
+        I, dA, dU = cf.gaussian_grad(wl.params[b], wl.d)
+        ref = np.concatenate([dA, dU])
+        tau = wl.rel_tol[b]
+        est_ok += abs(rg[b].estimate - I) <= tau * abs(I)
+        e = float(np.max(np.abs(G[b] - ref)) / np.max(np.abs(ref)))
+        gerr.append(e)
+        grad_ok += e <= 100 * tau
+    out = {"workload": "gaussian_grad_d6", "B": B, "slots_in_flight": slots,
+           "rel_tol": float(wl.rel_tol[0]),
+           "forward": {"evals_per_s": fe / tf, "wall_ms": 1e3 * tf},
+           "forward_adjoint": {"evals_per_s": fe / tg, "wall_ms": 1e3 * tg},
+           "adjoint_overhead": tg / tf - 1.0, "fevals": fe,
+           "same_run_with_adjoint": same,
+           "status_ok": sum(r.status_name == "OK" for r in rg),
+           "estimate_meets_closed_form": int(est_ok),
+           "gradient_within_100tau_of_closed_form": int(grad_ok),
+           "median_gradient_rel_err": float(np.median(gerr))}
+    if not args.no_plain:
+        t0 = time.perf_counter()
+        for b in range(B):
+            ctx.integrate_workload(wl.instance(b))
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        out["plain_sequential"] = {"evals_per_s": fe / tp, "wall_ms": 1e3 * tp}
+    ctx.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def adjoint_mode(args):
+    """The adjoint comparison alone (for profiling)."""
+    print(json.dumps({"mode": "adjoint", **adjoint(args)}), flush=True)
 
 
 def batched_mode(args):
@@ -232,11 +301,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", choices=["headline", "batched", "integrand", "copy"],
+    ap.add_argument("--mode", choices=["headline", "batched", "adjoint", "integrand",
+                                       "copy"],
                     default="headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-vs-plain comparison")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the forward-vs-forward+adjoint comparison")
     ap.add_argument("--no-plain", action="store_true",
                     help="batched run without the single-run comparison")
     ap.add_argument("--batch-count", type=int, default=0,
@@ -250,7 +322,8 @@ def main():
               "supported (the method's multi-GPU sharding is a design note, not code)",
               file=sys.stderr)
         sys.exit(2)
-    {"headline": headline, "batched": batched_mode, "integrand": integrand_mode,
+    {"headline": headline, "batched": batched_mode, "adjoint": adjoint_mode,
+     "integrand": integrand_mode,
      "copy": copy_mode}[args.mode](args)
 
 

@@ -167,6 +167,54 @@ int pg_integrate_batch(pg_context *ctx, int family, int dim, int B,
                        pg_result *out);
 
 /*
+ * Optional copy of the partition a run ends on (its leaves: every region
+ * finished on the way, by the relative-error test of Section 3.5.1 or a
+ * threshold of Algorithm 3, and the live list when the run stops). Device
+ * arrays owned by the caller: lo and w are structure-of-arrays [dim][ld]
+ * (leaf k, axis j at j * ld + k), owner[ld] the index in the batch of the
+ * integral a leaf belongs to (may be NULL). The run writes n leaves, in
+ * iteration order; it fails with PG_ENOMEM if more than ld would be needed.
+ */
+typedef struct {
+    double *lo;
+    double *w;
+    int32_t *owner;
+    int64_t ld;
+    int64_t n;          /* out */
+} pg_leaves;
+
+/*
+ * pg_integrate plus the derivative of the estimate with respect to the
+ * integrand's parameters (grad[n_params], host), taken over the partition
+ * the run ends on: the estimate is the sum of the degree-7 rule values of
+ * the leaves (Section 3.1: the finished regions' contributions plus the
+ * live list's), and each is a weighted sum of f at points that do not move
+ * with the parameters, so the derivative is the same weighted sum of
+ * df/dparameter. Families with parameter derivatives: product peak and
+ * Gaussian (a then u), oscillatory (a then u_1), corner peak (a);
+ * PG_EUNSUPPORTED otherwise. leaves may be NULL. Runs through the batched
+ * driver as a batch of one, so it takes the same decisions as
+ * pg_integrate_batch on this integral. Returns like pg_integrate.
+ */
+int pg_integrate_grad(pg_context *ctx, const pg_integrand *f,
+                      const double *lo, const double *hi,
+                      const pg_options *opt, pg_result *out, double *grad,
+                      pg_leaves *leaves);
+
+/*
+ * pg_integrate_batch plus each integral's parameter derivative over its
+ * own final partition, grad[b * n_params + k] (host). leaves (may be NULL)
+ * receives every integral's leaves, tagged by owner. Returns like
+ * pg_integrate_batch.
+ */
+int pg_integrate_batch_grad(pg_context *ctx, int family, int dim, int B,
+                            const double *params, int n_params,
+                            const double *lo, const double *hi,
+                            const double *rel_tol, const double *abs_tol,
+                            const pg_options *opt, pg_result *out,
+                            double *grad, pg_leaves *leaves);
+
+/*
  * View of the live region list as the last pg_integrate left it: the n
  * regions of its last iteration with their V, (refined) E, split axis K and
  * rel-err flags A. Device pointers, valid until the next call that uses the

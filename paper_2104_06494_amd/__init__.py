@@ -7,3 +7,4 @@ al. (SC'21) as hand-written gfx950 HIP kernels behind a C interface
 """
 from ._lib import FAMILY_ID, STATUS, PG_DIM_MAX, PG_DIM_MIN, LIB_PATH, load  # noqa: F401
 from .api import Context, IntegrateResult, PaganiError, context, integrate  # noqa: F401
+from .autograd import PaganiIntegral, integral  # noqa: F401

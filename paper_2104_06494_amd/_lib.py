@@ -23,7 +23,7 @@ EXPORTS = ["pg_default_options", "pg_workspace_bytes", "pg_context_create",
            "pg_context_destroy", "pg_context_set_stream", "pg_last_error",
            "pg_integrate", "pg_last_regions", "pg_evaluate", "pg_classify",
            "pg_threshold_search", "pg_filter_split", "pg_integrand_values",
-           "pg_integrate_batch"]
+           "pg_integrate_batch", "pg_integrate_grad", "pg_integrate_batch_grad"]
 
 
 class Integrand(C.Structure):
@@ -58,6 +58,11 @@ class RegionsView(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int64), ("ld", C.c_int64),
                 ("lo", C.c_void_p), ("w", C.c_void_p), ("V", C.c_void_p),
                 ("E", C.c_void_p), ("K", C.c_void_p), ("A", C.c_void_p)]
+
+
+class Leaves(C.Structure):
+    _fields_ = [("lo", C.c_void_p), ("w", C.c_void_p), ("owner", C.c_void_p),
+                ("ld", C.c_int64), ("n", C.c_int64)]
 
 
 _lib = None
@@ -97,6 +102,14 @@ def load():
                                      dp, dp, dp, dp, C.POINTER(Options),
                                      C.POINTER(Result)]
     L.pg_integrate_batch.restype = C.c_int
+    L.pg_integrate_grad.argtypes = [vp, C.POINTER(Integrand), dp, dp,
+                                    C.POINTER(Options), C.POINTER(Result), dp,
+                                    C.POINTER(Leaves)]
+    L.pg_integrate_grad.restype = C.c_int
+    L.pg_integrate_batch_grad.argtypes = [vp, C.c_int, C.c_int, C.c_int, dp, C.c_int,
+                                          dp, dp, dp, dp, C.POINTER(Options),
+                                          C.POINTER(Result), dp, C.POINTER(Leaves)]
+    L.pg_integrate_batch_grad.restype = C.c_int
     L.pg_last_regions.argtypes = [vp, C.POINTER(RegionsView)]
     L.pg_last_regions.restype = C.c_int
     L.pg_evaluate.argtypes = [vp, C.POINTER(Integrand), i64, vp, vp, i64, vp,

@@ -164,6 +164,70 @@ class Context:
         [B, n_params], rel_tol a scalar or [B], abs_tol None (1e-20), a
         scalar or [B]; all share the box [lo, hi] and the options, and
         max_regions is the cap of each. Returns a list of B results."""
+        return self._batch(family, d, params, rel_tol, abs_tol, lo, hi, init_splits,
+                           max_iters, relerr_filter, threshold_filter, max_regions)[0]
+
+    def integrate_batch_grad(self, family, d, params, rel_tol, abs_tol=None,
+                             lo=None, hi=None, init_splits=4, max_iters=100,
+                             relerr_filter=1, threshold_filter=1, max_regions=0,
+                             leaves_capacity=0):
+        """integrate_batch plus dI/dparams of every integral over its final
+        partition: returns (results, grad [B, n_params] numpy, leaves). With
+        leaves_capacity > 0, leaves is a dict of device tensors lo, w [d, n]
+        and owner [n] (the partition's regions); otherwise None."""
+        return self._batch(family, d, params, rel_tol, abs_tol, lo, hi, init_splits,
+                           max_iters, relerr_filter, threshold_filter, max_regions,
+                           grad=True, leaves_capacity=leaves_capacity)
+
+    def integrate_grad(self, family, d, params, lo=None, hi=None, rel_tol=1e-3,
+                       abs_tol=1e-20, init_splits=4, max_iters=100, relerr_filter=1,
+                       threshold_filter=1, max_regions=0, leaves_capacity=0):
+        """One integral and its parameter derivative through the C entry
+        point pg_integrate_grad: returns (result, grad [n_params], leaves)."""
+        self._bind_stream()
+        f, keep = _integrand(family, d, params)
+        lo = np.zeros(d) if lo is None else np.asarray(lo, dtype=np.float64)
+        hi = np.ones(d) if hi is None else np.asarray(hi, dtype=np.float64)
+        clo = (C.c_double * d)(*lo.tolist())
+        chi = (C.c_double * d)(*hi.tolist())
+        o = L.Options()
+        self.lib.pg_default_options(C.byref(o))
+        o.rel_tol, o.abs_tol = float(rel_tol), float(abs_tol)
+        o.init_splits, o.max_iters = int(init_splits), int(max_iters)
+        o.relerr_filter, o.threshold_filter = int(relerr_filter), int(threshold_filter)
+        o.max_regions = int(max_regions)
+        g = np.zeros(f.n_params)
+        lv, lt = self._leaves(d, leaves_capacity)
+        r = L.Result()
+        with torch.cuda.device(self.device):
+            rc = self.lib.pg_integrate_grad(self.h, C.byref(f), clo, chi, C.byref(o),
+                                            C.byref(r), g.ctypes.data_as(C.POINTER(C.c_double)),
+                                            C.byref(lv) if lv is not None else None)
+        if rc < 0:
+            raise self._err(rc)
+        return IntegrateResult(**r.as_dict()), g, self._leaves_view(lv, lt)
+
+    def _leaves(self, d, cap):
+        if not cap:
+            return None, None
+        cap = int(cap)
+        lo = torch.empty((d, cap), dtype=torch.float64, device=self.device)
+        w = torch.empty((d, cap), dtype=torch.float64, device=self.device)
+        owner = torch.empty(cap, dtype=torch.int32, device=self.device)
+        lv = L.Leaves(lo.data_ptr(), w.data_ptr(), owner.data_ptr(), cap, 0)
+        return lv, (lo, w, owner)
+
+    @staticmethod
+    def _leaves_view(lv, lt):
+        if lv is None:
+            return None
+        lo, w, owner = lt
+        n = lv.n
+        return {"n": n, "lo": lo[:, :n], "w": w[:, :n], "owner": owner[:n]}
+
+    def _batch(self, family, d, params, rel_tol, abs_tol, lo, hi, init_splits,
+               max_iters, relerr_filter, threshold_filter, max_regions, grad=False,
+               leaves_capacity=0):
         self._bind_stream()
         P = np.ascontiguousarray(np.atleast_2d(np.asarray(params, dtype=np.float64)))
         B, npar = P.shape
@@ -186,23 +250,36 @@ class Context:
         o.max_regions = int(max_regions)
         res = (L.Result * B)()
         fam = L.FAMILY_ID[family] if isinstance(family, str) else int(family)
+        g = np.zeros((B, npar)) if grad else None
+        lv, lt = self._leaves(d, leaves_capacity) if grad else (None, None)
         with torch.cuda.device(self.device):
-            rc = self.lib.pg_integrate_batch(self.h, fam, int(d), int(B), cp, int(npar),
-                                             clo, chi, crt, cat, C.byref(o), res)
+            if grad:
+                rc = self.lib.pg_integrate_batch_grad(
+                    self.h, fam, int(d), int(B), cp, int(npar), clo, chi, crt, cat,
+                    C.byref(o), res, g.ctypes.data_as(C.POINTER(C.c_double)),
+                    C.byref(lv) if lv is not None else None)
+            else:
+                rc = self.lib.pg_integrate_batch(self.h, fam, int(d), int(B), cp,
+                                                 int(npar), clo, chi, crt, cat,
+                                                 C.byref(o), res)
         if rc < 0:
             raise self._err(rc)
-        return [IntegrateResult(**res[b].as_dict()) for b in range(B)]
+        results = [IntegrateResult(**res[b].as_dict()) for b in range(B)]
+        return results, g, self._leaves_view(lv, lt)
 
-    def integrate_batch_workload(self, wl, count=None):
-        """integrate_batch over a batched workload (its first `count`
-        integrals if given)."""
+    def integrate_batch_workload(self, wl, count=None, grad=False, leaves_capacity=0):
+        """integrate_batch (or integrate_batch_grad with grad=True) over a
+        batched workload (its first `count` integrals if given)."""
         B = wl.B if count is None else int(count)
-        return self.integrate_batch(wl.family, wl.d, wl.params[:B], wl.rel_tol[:B],
-                                    wl.abs_tol[:B], wl.lo, wl.hi, init_splits=wl.init_splits,
-                                    max_iters=wl.max_iters,
-                                    relerr_filter=wl.relerr_filter,
-                                    threshold_filter=wl.threshold_filter,
-                                    max_regions=wl.max_regions)
+        fn = self.integrate_batch
+        kw = {}
+        if grad:
+            fn = self.integrate_batch_grad
+            kw["leaves_capacity"] = leaves_capacity
+        return fn(wl.family, wl.d, wl.params[:B], wl.rel_tol[:B], wl.abs_tol[:B],
+                  wl.lo, wl.hi, init_splits=wl.init_splits, max_iters=wl.max_iters,
+                  relerr_filter=wl.relerr_filter, threshold_filter=wl.threshold_filter,
+                  max_regions=wl.max_regions, **kw)
 
     def integrate_workload(self, wl, **kw) -> IntegrateResult:
         args = dict(rel_tol=wl.rel_tol, abs_tol=wl.abs_tol,

@@ -5,7 +5,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", s) for s in ("pg_evaluate.hip", "pg_list.hip", "pg_batch.hip", "pg_api.hip")]
+SOURCES = [os.path.join(HERE, "csrc", s) for s in ("pg_evaluate.hip", "pg_list.hip", "pg_batch.hip", "pg_adjoint.hip",
+                                                     "pg_api.hip")]
 LIB = os.path.join(HERE, "libpagani.so")
 ARCH = os.environ.get("PAGANI_OFFLOAD_ARCH", "gfx950")
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",

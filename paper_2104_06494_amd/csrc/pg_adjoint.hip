@@ -1,0 +1,352 @@
+// pg_adjoint.hip -- gfx950 kernels for the parameter derivative of the
+// estimate over the partition a run converges on.
+//
+// The estimate is the sum of the degree-7 rule values of the partition's
+// leaves (every region finished on the way, and the live list when the run
+// ends). Each rule value is a weighted sum of f at points that do not move
+// with the parameters, so dI/dtheta is the same weighted sum of df/dtheta
+// over the leaves' points. The leaves of an iteration are still in the
+// current list when its decisions are known, so the derivative is
+// accumulated there, one launch per iteration, and no leaf is stored
+// (unless the caller asks for the partition itself).
+//
+// Layout: one block per (segment, quarter): the block finds the segment's
+// leaves (ballot prefix into LDS), then one lane per leaf walks the leaf's
+// points; partial sums per block in a fixed order, then per integral.
+#include "pg_device.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+namespace pg {
+
+namespace {
+
+// Waves each SIMD must be able to hold (caps the registers of a lane at
+// 512 / ADJ_WAVES_PER_SIMD): the point walk is a chain of dependent FP64
+// operations, and more resident waves hide their latency.
+constexpr int ADJ_WAVES_PER_SIMD = 2;
+
+// Parameters in the number the derivative kernels read them:
+//   product peak: p[k] = a_k^-2, p[d+k] = u_k, p[2d+k] = 2 a_k^-3
+//   gaussian:     p[k] = a_k,    p[d+k] = u_k
+//   oscillatory:  p[k] = a_k,    p[d]   = 2 pi u_1
+//   corner peak:  p[k] = a_k
+template <int FAM, int D>
+constexpr int n_grad() {
+    return (FAM == PG_PRODUCT_PEAK || FAM == PG_GAUSSIAN) ? 2 * D
+           : FAM == PG_OSCILLATORY ? D + 1 : D;
+}
+
+// g += wgt * df/dtheta at x (derivatives of the integrand families with
+// respect to their user parameters).
+template <int FAM, int D>
+__device__ __forceinline__ void point_grad(const double (&x)[D],
+                                           const GParams &P, double wgt,
+                                           double *g) {
+    if constexpr (FAM == PG_GAUSSIAN) {
+        // f = exp(-sum a^2 t^2), t = x - u: d/da = -2 a t^2 f, d/du = 2 a^2 t f
+        double t[D], s = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            t[k] = x[k] - P.p[D + k];
+            const double at = P.p[k] * t[k];
+            s = fma(at, at, s);
+        }
+        const double wf = wgt * exp(-s);
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const double at = P.p[k] * t[k];
+            g[k] = fma(-2.0 * at * t[k], wf, g[k]);
+            g[D + k] = fma(2.0 * at * P.p[k], wf, g[D + k]);
+        }
+    } else if constexpr (FAM == PG_PRODUCT_PEAK) {
+        // f = prod r_k, r_k = 1 / (a^-2 + t^2): d/da = f (2 a^-3) r_k,
+        // d/du = f 2 t r_k
+        double t[D], r[D], f = 1.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            t[k] = x[k] - P.p[D + k];
+            r[k] = 1.0 / fma(t[k], t[k], P.p[k]);
+            f *= r[k];
+        }
+        const double wf = wgt * f;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const double wr = wf * r[k];
+            g[k] = fma(P.p[2 * D + k], wr, g[k]);
+            g[D + k] = fma(2.0 * t[k], wr, g[D + k]);
+        }
+    } else if constexpr (FAM == PG_OSCILLATORY) {
+        // f = cos(phi), phi = 2 pi u_1 + sum a x: d/da = -x sin, d/du_1 = -2 pi sin
+        double phi = P.p[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) phi = fma(P.p[k], x[k], phi);
+        const double ws = wgt * sin(phi);
+#pragma unroll
+        for (int k = 0; k < D; ++k) g[k] = fma(-x[k], ws, g[k]);
+        g[D] = fma(-2.0 * M_PI, ws, g[D]);
+    } else {
+        // f = s^-(d+1), s = 1 + sum a x: d/da = -(d+1) x s^-(d+2)
+        double s = 1.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) s = fma(P.p[k], x[k], s);
+        const double r = 1.0 / s;
+        double f = r;
+#pragma unroll
+        for (int k = 1; k < D + 2; ++k) f *= r;
+        const double wf = -(double)(D + 1) * wgt * f;
+#pragma unroll
+        for (int k = 0; k < D; ++k) g[k] = fma(x[k], wf, g[k]);
+    }
+}
+
+// Derivative of one region's rule value without the volume factor. The
+// points are walked in the evaluation's work units of four (one axis:
+// +-lambda2, +-lambda3; one pair of axes: the four sign choices of lambda4;
+// four sign vectors of lambda5) plus the centre; the unit index is the same
+// on every lane, so signs are chosen in scalar registers and each
+// coordinate is one FMA, x_k = c_k + s_k (lambda h_k), rounded as the
+// evaluation rounds it.
+template <int FAM, int D>
+__device__ __forceinline__ void region_grad(const double (&c)[D],
+                                            const double (&h)[D],
+                                            const GParams &P, const Rule &R,
+                                            double *g) {
+    constexpr int NPAIR = D * (D - 1) / 2;
+    constexpr int N5 = (1 << D) / 4;
+    constexpr int U = D + NPAIR + N5;
+    point_grad<FAM, D>(c, P, R.w7[0], g);
+    for (int u = 0; u < U; ++u) {
+        double x[D];
+        if (u < D) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double lam = q < 2 ? R.lam2 : R.lam3;
+                const double sg = (q & 1) ? -1.0 : 1.0;
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+                    x[k] = fma(k == u ? sg : 0.0, lam * h[k], c[k]);
+                point_grad<FAM, D>(x, P, q < 2 ? R.w7[1] : R.w7[2], g);
+            }
+        } else if (u < D + NPAIR) {
+            int i = 0, rem = u - D;
+            while (rem >= D - 1 - i) { rem -= D - 1 - i; ++i; }
+            const int j = i + 1 + rem;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double si = (q & 2) ? -1.0 : 1.0;
+                const double sj = (q & 1) ? -1.0 : 1.0;
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+                    x[k] = fma(k == i ? si : (k == j ? sj : 0.0), R.lam4 * h[k],
+                               c[k]);
+                point_grad<FAM, D>(x, P, R.w7[3], g);
+            }
+        } else {
+            const int m = u - D - NPAIR;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int b = 4 * m + q;
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+                    x[k] = fma(((b >> k) & 1) ? -1.0 : 1.0, R.lam5 * h[k], c[k]);
+                point_grad<FAM, D>(x, P, R.w7[4], g);
+            }
+        }
+    }
+}
+
+// Leaves of one segment: every region of an integral that ends this
+// iteration; otherwise the regions that are not active (active: A_rel, and
+// E > t_acc after an accepted threshold -- the count pass's test).
+template <int FAM, int D>
+__global__ void __launch_bounds__(LIST_THREADS, ADJ_WAVES_PER_SIMD)
+k_batch_adjoint(const BSeg *__restrict__ segs, const BInst *__restrict__ inst,
+                const SearchState *__restrict__ states,
+                const uint8_t *__restrict__ A_rel, const double *__restrict__ E,
+                const double *__restrict__ lo, const double *__restrict__ w,
+                int64_t ld, const GParams *__restrict__ gtab, const Rule R,
+                double *__restrict__ gpart, int64_t ncol,
+                const uint32_t *__restrict__ offsets, LeafOut out) {
+    constexpr int NP = n_grad<FAM, D>();
+    constexpr int NW = LIST_THREADS / 64;
+    __shared__ uint16_t idx[SEG];
+    __shared__ uint32_t wtot[NW];
+    __shared__ double red[NW][NP];
+    const int64_t s = blockIdx.x / ADJ_SPLIT;
+    const int part = blockIdx.x % ADJ_SPLIT;
+    const BSeg sg = segs[s];
+    const BInst &I = inst[sg.slot];
+    const SearchState &S = states[sg.slot];
+    const int mode = !I.live ? 0 : ((I.searching && S.ok) ? 2 : 1);
+    const double t = S.t_acc;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    uint32_t nleaf = 0;
+    for (int64_t c0 = sg.start; c0 < sg.end; c0 += LIST_THREADS) {
+        const int64_t i = c0 + threadIdx.x;
+        bool leaf = false;
+        if (i < sg.end) {
+            if (mode == 0) {
+                leaf = true;
+            } else {
+                const bool act = A_rel[i] && (mode == 1 || E[i] > t);
+                leaf = !act;
+            }
+        }
+        const uint64_t b = __ballot(leaf);
+        const uint32_t pre = (uint32_t)__popcll(b & ((1ull << lane) - 1ull));
+        if (lane == 0) wtot[wave] = (uint32_t)__popcll(b);
+        __syncthreads();
+        uint32_t base = nleaf, tot = 0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            if (q < wave) base += wtot[q];
+            tot += wtot[q];
+        }
+        if (leaf) idx[base + pre] = (uint16_t)(i - sg.start);
+        nleaf += tot;
+        __syncthreads();
+    }
+    const GParams P = gtab[sg.slot];
+    // leaves of this segment before it in its integral's leaf order
+    const int64_t leaf0 = I.fin_base + (sg.start - I.start) -
+                          (mode == 0 ? 0 : (int64_t)offsets[s]);
+    double G[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) G[q] = 0.0;
+    for (uint32_t j = part * LIST_THREADS + threadIdx.x; j < nleaf;
+         j += ADJ_SPLIT * LIST_THREADS) {
+        const int64_t i = sg.start + idx[j];
+        double c[D], h[D], vol = 1.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const double wk = w[k * ld + i], lk = lo[k * ld + i];
+            h[k] = wk * 0.5;
+            c[k] = lk + h[k];
+            vol *= wk;
+            if (out.lo) {
+                const int64_t pos = out.base + leaf0 + j;
+                out.lo[k * out.ld + pos] = lk;
+                out.w[k * out.ld + pos] = wk;
+            }
+        }
+        if (out.owner) out.owner[out.base + leaf0 + j] = I.owner;
+        double g[NP];
+#pragma unroll
+        for (int q = 0; q < NP; ++q) g[q] = 0.0;
+        region_grad<FAM, D>(c, h, P, R, g);
+#pragma unroll
+        for (int q = 0; q < NP; ++q) G[q] = fma(vol, g[q], G[q]);
+    }
+    // fixed-order block sum: butterfly within waves, then waves in order
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        double v = G[q];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) red[wave][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < NP) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) v += red[q][threadIdx.x];
+        gpart[(int64_t)threadIdx.x * ncol + blockIdx.x] = v;
+    }
+}
+
+// Per integral: its columns of gpart added in a fixed order.
+__global__ void __launch_bounds__(LIST_THREADS)
+k_batch_grad_reduce(const int32_t *__restrict__ order,
+                    const BInst *__restrict__ inst, int np,
+                    const double *__restrict__ gpart, int64_t ncol,
+                    double *__restrict__ git) {
+    __shared__ double red[LIST_THREADS];
+    const int slot = order[blockIdx.x];
+    const BInst &I = inst[slot];
+    const int64_t c0 = I.seg0 * ADJ_SPLIT, c1 = (I.seg0 + I.nseg) * ADJ_SPLIT;
+    for (int q = 0; q < np; ++q) {
+        double v = 0.0;
+        for (int64_t c = c0 + threadIdx.x; c < c1; c += LIST_THREADS)
+            v += gpart[(int64_t)q * ncol + c];
+        red[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = LIST_THREADS / 2; o >= 1; o >>= 1) {
+            if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) git[(int64_t)slot * GRAD_MAX + q] = red[0];
+        __syncthreads();
+    }
+}
+
+using AdjFn = void (*)(const BSeg *, const BInst *, const SearchState *,
+                       const uint8_t *, const double *, const double *,
+                       const double *, int64_t, const GParams *, const Rule,
+                       double *, int64_t, const uint32_t *, LeafOut);
+
+template <int FAM, int... Ds>
+constexpr AdjFn pick(int d, std::integer_sequence<int, Ds...>) {
+    AdjFn f = nullptr;
+    ((f = (d == Ds ? &k_batch_adjoint<FAM, Ds> : f)), ...);
+    return f;
+}
+
+AdjFn adjoint_kernel(int family, int d) {
+    using Dims = std::integer_sequence<int, 2, 3, 4, 5, 6, 7, 8, 9, 10>;
+    switch (family) {
+    case PG_PRODUCT_PEAK: return pick<PG_PRODUCT_PEAK>(d, Dims{});
+    case PG_GAUSSIAN: return pick<PG_GAUSSIAN>(d, Dims{});
+    case PG_OSCILLATORY: return pick<PG_OSCILLATORY>(d, Dims{});
+    case PG_CORNER_PEAK: return pick<PG_CORNER_PEAK>(d, Dims{});
+    default: return nullptr;
+    }
+}
+
+}  // namespace
+
+int grad_nparams(int family, int d) {
+    switch (family) {
+    case PG_PRODUCT_PEAK: case PG_GAUSSIAN: return 2 * d;
+    case PG_OSCILLATORY: return d + 1;
+    case PG_CORNER_PEAK: return d;
+    default: return -1;
+    }
+}
+
+bool adjoint_supported(int family, int d) {
+    return d >= PG_DIM_MIN && d <= PG_DIM_MAX && adjoint_kernel(family, d);
+}
+
+hipError_t launch_batch_adjoint(hipStream_t st, int family, int d,
+                                int64_t nseg, const BSeg *segs,
+                                const BInst *inst, const SearchState *states,
+                                const uint8_t *A_rel, const double *E,
+                                const double *lo, const double *w, int64_t ld,
+                                const GParams *gtab, const Rule &R,
+                                double *gpart, const uint32_t *offsets,
+                                const LeafOut &out) {
+    if (nseg <= 0) return hipSuccess;
+    AdjFn k = adjoint_kernel(family, d);
+    if (!k) return hipErrorInvalidValue;
+    const int64_t ncol = nseg * ADJ_SPLIT;
+    hipLaunchKernelGGL(k, dim3((unsigned)ncol), dim3(LIST_THREADS), 0, st,
+                       segs, inst, states, A_rel, E, lo, w, ld, gtab, R, gpart,
+                       ncol, offsets, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_grad_reduce(hipStream_t st, int nslots,
+                                    const int32_t *order, const BInst *inst,
+                                    int np, const double *gpart, int64_t nseg,
+                                    double *git) {
+    if (nslots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_grad_reduce, dim3(nslots), dim3(LIST_THREADS), 0,
+                       st, order, inst, np, gpart, nseg * ADJ_SPLIT, git);
+    return hipGetLastError();
+}
+
+}  // namespace pg

@@ -50,6 +50,10 @@ struct pg_context {
     BCls *b_cls = nullptr;
     double *b_tpart = nullptr;
     int64_t nseg_max = 0;
+    // parameter derivative over the final partition
+    GParams *b_gtable = nullptr, *hb_gtable = nullptr;
+    double *b_gpart = nullptr;
+    double *b_git = nullptr, *hb_git = nullptr;
     std::vector<hipEvent_t> events;
     std::string err;
     // live list left by the last pg_integrate
@@ -60,12 +64,15 @@ struct pg_context {
 namespace {
 
 constexpr size_t ALIGN = 256;
+// Pinned staging copies of the slot table, used in turn (a copy is reused
+// only after a stream synchronisation has passed since its last upload).
+constexpr int INST_STAGES = 4;
 
 struct Layout {
     size_t lo[2], w[2], V, E, Vp, K, A, A2;
     size_t pv, pe, pav, pae, pmin, pmax, pcnt, off;
     size_t inst[2], b_inst, b_state, b_tot, b_table, b_order, b_new, b_segs,
-        b_cls, b_tpart;
+        b_cls, b_tpart, b_gtable, b_gpart, b_git;
     size_t search_part, dtot, dstate, total;
     int64_t nseg;
 };
@@ -113,6 +120,9 @@ Layout layout(int dim_max, int64_t cap) {
     L.b_segs = bump(at, sizeof(BSeg) * L.nseg);
     L.b_cls = bump(at, sizeof(BCls) * L.nseg);
     L.b_tpart = bump(at, sizeof(double) * 2 * TRIAL_M * L.nseg);
+    L.b_gtable = bump(at, sizeof(GParams) * BATCH_MAX_SLOTS);
+    L.b_gpart = bump(at, sizeof(double) * GRAD_MAX * ADJ_SPLIT * L.nseg);
+    L.b_git = bump(at, sizeof(double) * GRAD_MAX * BATCH_MAX_SLOTS);
     L.dtot = bump(at, sizeof(Totals));
     L.dstate = bump(at, sizeof(SearchState));
     L.total = (at + ALIGN - 1) / ALIGN * ALIGN;
@@ -217,6 +227,31 @@ int make_params(pg_context *ctx, const pg_integrand *f, FParams *P) {
         break;
     }
     return PG_OK;
+}
+
+// Parameters of the derivative kernels (layout: see pg_adjoint.hip). The
+// values were validated by make_params.
+void make_gparams(int family, int d, const double *p, GParams *G) {
+    std::memset(G, 0, sizeof *G);
+    switch (family) {
+    case PG_PRODUCT_PEAK:
+        for (int k = 0; k < d; ++k) {
+            G->p[k] = 1.0 / (p[k] * p[k]);
+            G->p[d + k] = p[d + k];
+            G->p[2 * d + k] = 2.0 / (p[k] * p[k] * p[k]);
+        }
+        break;
+    case PG_GAUSSIAN:
+        for (int k = 0; k < 2 * d; ++k) G->p[k] = p[k];
+        break;
+    case PG_OSCILLATORY:
+        for (int k = 0; k < d; ++k) G->p[k] = p[k];
+        G->p[d] = 2.0 * M_PI * p[d];
+        break;
+    default:
+        for (int k = 0; k < d; ++k) G->p[k] = p[k];
+        break;
+    }
 }
 
 // Waves per evaluation block: enough blocks x waves to cover the chip twice
@@ -368,8 +403,14 @@ int pg_context_create(int device, int dim_max, int64_t capacity,
     if (hipHostMalloc((void **)&ctx->htot, sizeof(Totals), 0) != hipSuccess ||
         hipHostMalloc((void **)&ctx->hstate, sizeof(SearchState), 0) !=
             hipSuccess ||
-        hipHostMalloc((void **)&ctx->hb_inst, sizeof(BInst) * 2 * BATCH_MAX_SLOTS,
+        hipHostMalloc((void **)&ctx->hb_inst,
+                      sizeof(BInst) * INST_STAGES * BATCH_MAX_SLOTS,
                       0) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->hb_gtable,
+                      sizeof(GParams) * BATCH_MAX_SLOTS, 0) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->hb_git,
+                      sizeof(double) * GRAD_MAX * BATCH_MAX_SLOTS, 0) !=
+            hipSuccess ||
         hipHostMalloc((void **)&ctx->hb_state,
                       sizeof(SearchState) * BATCH_MAX_SLOTS, 0) != hipSuccess ||
         hipHostMalloc((void **)&ctx->hb_tot, sizeof(Totals) * BATCH_MAX_SLOTS,
@@ -413,6 +454,9 @@ int pg_context_create(int device, int dim_max, int64_t capacity,
     ctx->b_segs = (BSeg *)(b + L.b_segs);
     ctx->b_cls = (BCls *)(b + L.b_cls);
     ctx->b_tpart = (double *)(b + L.b_tpart);
+    ctx->b_gtable = (GParams *)(b + L.b_gtable);
+    ctx->b_gpart = (double *)(b + L.b_gpart);
+    ctx->b_git = (double *)(b + L.b_git);
     ctx->nseg_max = L.nseg;
     ctx->dtot = (Totals *)(b + L.dtot);
     ctx->dstate = (SearchState *)(b + L.dstate);
@@ -428,7 +472,7 @@ void pg_context_destroy(pg_context *ctx) {
     if (ctx->htot) (void)hipHostFree(ctx->htot);
     if (ctx->hstate) (void)hipHostFree(ctx->hstate);
     void *pinned[] = {ctx->hb_inst, ctx->hb_state, ctx->hb_tot, ctx->hb_table,
-                      ctx->hb_order, ctx->hb_new};
+                      ctx->hb_order, ctx->hb_new, ctx->hb_gtable, ctx->hb_git};
     for (void *q : pinned)
         if (q) (void)hipHostFree(q);
     if (ctx->own_ws && ctx->ws) (void)hipFree(ctx->ws);
@@ -833,11 +877,14 @@ int pg_integrate(pg_context *ctx, const pg_integrand *f, const double *lo,
 // tolerance, cap and state; they share every kernel launch. At most
 // min(B, capacity / cap, BATCH_MAX_SLOTS) integrals are live at once (each
 // may grow to `cap` regions); the others start as slots free up.
-int pg_integrate_batch(pg_context *ctx, int family, int dim, int B,
-                       const double *params, int n_params, const double *lo,
-                       const double *hi, const double *rel_tol,
-                       const double *abs_tol, const pg_options *opt,
-                       pg_result *out) {
+// With grad, each iteration also adds the parameter derivative of the rule
+// values of the regions that leave the list for good (the leaves of the
+// final partition, see pg_adjoint.hip); with leaves, those are copied out.
+static int run_batch(pg_context *ctx, int family, int dim, int B,
+                     const double *params, int n_params, const double *lo,
+                     const double *hi, const double *rel_tol,
+                     const double *abs_tol, const pg_options *opt,
+                     pg_result *out, double *grad, pg_leaves *leaves) {
     if (!ctx) return PG_EINVAL;
     ctx->err.clear();
     if (B < 1 || !params || !rel_tol || !out || !lo || !hi)
@@ -853,6 +900,21 @@ int pg_integrate_batch(pg_context *ctx, int family, int dim, int B,
         if (rc) return rc;
         if (!(rel_tol[b] > 0.0) && !((abs_tol ? abs_tol[b] : o.abs_tol) > 0.0))
             return fail(ctx, PG_EINVAL, "integral %d has no positive tolerance", b);
+    }
+    const bool want_grad = grad != nullptr || leaves != nullptr;
+    std::vector<GParams> gp;
+    if (want_grad) {
+        if (!adjoint_supported(family, d) || grad_nparams(family, d) != n_params)
+            return fail(ctx, PG_EUNSUPPORTED,
+                        "no parameter derivative for family %d", family);
+        if (leaves && (!leaves->lo || !leaves->w || leaves->ld < 0))
+            return fail(ctx, PG_EINVAL, "leaves: NULL array or ld < 0");
+        gp.resize(B);
+        for (int b = 0; b < B; ++b)
+            make_gparams(family, d, params + (size_t)b * n_params, &gp[b]);
+        if (grad)
+            for (size_t q = 0; q < (size_t)B * n_params; ++q) grad[q] = 0.0;
+        if (leaves) leaves->n = 0;
     }
     for (int k = 0; k < d; ++k)
         if (!(lo[k] < hi[k]) || !std::isfinite(lo[k]) || !std::isfinite(hi[k]))
@@ -898,13 +960,26 @@ int pg_integrate_batch(pg_context *ctx, int family, int dim, int B,
     }
     int next_b = 0;
     int cur = 0;
-    // host copy of the slot table; every upload goes through one of two
-    // pinned staging halves in turn (between two uploads from the same half
-    // there is always a stream synchronisation)
+    // host copy of the slot table; every upload goes through the pinned
+    // staging copies in turn (at most two uploads in a row are not separated
+    // by a stream synchronisation, so a copy is never rewritten while its
+    // last upload may still be pending)
     std::vector<BInst> HIv(K);
     BInst *HI = HIv.data();
     int stage = 0;
     std::vector<Totals> Tc(K);                  // classify totals per slot
+    // derivative sums of the last adjoint launch, read after the next
+    // synchronisation: (slot, integral) pairs they belong to
+    std::vector<std::pair<int, int>> git_owner;
+    int64_t n_leaves = 0;
+    auto take_git = [&]() {
+        if (grad)
+            for (auto &sb : git_owner)
+                for (int q = 0; q < n_params; ++q)
+                    grad[(size_t)sb.second * n_params + q] +=
+                        ctx->hb_git[(size_t)sb.first * GRAD_MAX + q];
+        git_owner.clear();
+    };
     auto finish = [&](int k, int status) {
         Slot &S = slots[k];
         pg_result &r = out[S.b];
@@ -931,6 +1006,7 @@ int pg_integrate_batch(pg_context *ctx, int family, int dim, int B,
             S.start = running;
             S.n = g_d;
             ctx->hb_table[k] = fp[S.b];
+            if (want_grad) ctx->hb_gtable[k] = gp[S.b];
             std::memset(&HI[k], 0, sizeof(BInst));
             HI[k].out_start = running;
             ctx->hb_new[nnew++] = k;
@@ -940,7 +1016,7 @@ int pg_integrate_batch(pg_context *ctx, int family, int dim, int B,
     };
     auto upload_inst = [&]() -> int {
         BInst *h = ctx->hb_inst + (size_t)stage * BATCH_MAX_SLOTS;
-        stage = 1 - stage;
+        stage = (stage + 1) % INST_STAGES;
         std::memcpy(h, HI, sizeof(BInst) * K);
         HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->b_inst, h, sizeof(BInst) * K,
                                         hipMemcpyHostToDevice, st));
@@ -957,6 +1033,10 @@ int pg_integrate_batch(pg_context *ctx, int family, int dim, int B,
         HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->b_table, ctx->hb_table,
                                         sizeof(FParams) * K,
                                         hipMemcpyHostToDevice, st));
+        if (want_grad)
+            HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->b_gtable, ctx->hb_gtable,
+                                            sizeof(GParams) * K,
+                                            hipMemcpyHostToDevice, st));
         HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->b_new, ctx->hb_new,
                                         sizeof(int32_t) * nnew,
                                         hipMemcpyHostToDevice, st));
@@ -1025,6 +1105,7 @@ int pg_integrate_batch(pg_context *ctx, int family, int dim, int B,
                                         sizeof(Totals) * K,
                                         hipMemcpyDeviceToHost, st));
         HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
+        take_git();
         // ---- termination test and threshold triggers, per slot
         int searching = 0;
         for (int k : order) {
@@ -1143,6 +1224,42 @@ int pg_integrate_batch(pg_context *ctx, int family, int dim, int B,
             S.paired = 1;
             next_order.push_back(k);
         }
+        // ---- derivative over this iteration's leaves: all regions of an
+        // integral that ends, the non-survivors of the others
+        if (want_grad) {
+            int64_t fin = 0;
+            for (int k : order) {
+                BInst &I = HI[k];
+                I.fin_base = fin;
+                I.owner = slots[k].b;
+                fin += I.live ? I.n - I.na : I.n;
+                git_owner.emplace_back(k, slots[k].b);
+            }
+            if (leaves && n_leaves + fin > leaves->ld)
+                return fail(ctx, PG_ENOMEM, "more than %lld leaves",
+                            (long long)leaves->ld);
+            BRUN(upload_inst());
+            LeafOut lout{};
+            if (leaves) {
+                lout.lo = leaves->lo;
+                lout.w = leaves->w;
+                lout.owner = leaves->owner;
+                lout.ld = leaves->ld;
+                lout.base = n_leaves;
+            }
+            HIP_OR_FAIL(ctx, launch_batch_adjoint(
+                                 st, family, d, nseg, ctx->b_segs, ctx->b_inst,
+                                 ctx->b_state, ctx->A, ctx->E, ctx->lo[cur],
+                                 ctx->w[cur], ld, ctx->b_gtable, R,
+                                 ctx->b_gpart, ctx->off, lout));
+            HIP_OR_FAIL(ctx, launch_batch_grad_reduce(
+                                 st, nslots, ctx->b_order, ctx->b_inst,
+                                 n_params, ctx->b_gpart, nseg, ctx->b_git));
+            HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->hb_git, ctx->b_git,
+                                            sizeof(double) * GRAD_MAX * K,
+                                            hipMemcpyDeviceToHost, st));
+            n_leaves += fin;
+        }
         order.swap(next_order);
         admit();
         BRUN(upload_inst());
@@ -1156,6 +1273,10 @@ int pg_integrate_batch(pg_context *ctx, int family, int dim, int B,
             HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->b_table, ctx->hb_table,
                                             sizeof(FParams) * K,
                                             hipMemcpyHostToDevice, st));
+            if (want_grad)
+                HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->b_gtable, ctx->hb_gtable,
+                                                sizeof(GParams) * K,
+                                                hipMemcpyHostToDevice, st));
             HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->b_new, ctx->hb_new,
                                             sizeof(int32_t) * nnew,
                                             hipMemcpyHostToDevice, st));
@@ -1168,8 +1289,51 @@ int pg_integrate_batch(pg_context *ctx, int family, int dim, int B,
         n_total = running;
     }
     HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
+    take_git();
+    if (leaves) leaves->n = n_leaves;
 #undef BRUN
     return PG_OK;
+}
+
+int pg_integrate_batch(pg_context *ctx, int family, int dim, int B,
+                       const double *params, int n_params, const double *lo,
+                       const double *hi, const double *rel_tol,
+                       const double *abs_tol, const pg_options *opt,
+                       pg_result *out) {
+    return run_batch(ctx, family, dim, B, params, n_params, lo, hi, rel_tol,
+                     abs_tol, opt, out, nullptr, nullptr);
+}
+
+int pg_integrate_batch_grad(pg_context *ctx, int family, int dim, int B,
+                            const double *params, int n_params,
+                            const double *lo, const double *hi,
+                            const double *rel_tol, const double *abs_tol,
+                            const pg_options *opt, pg_result *out,
+                            double *grad, pg_leaves *leaves) {
+    if (!grad) {
+        if (ctx) ctx->err = "grad is NULL";
+        return PG_EINVAL;
+    }
+    return run_batch(ctx, family, dim, B, params, n_params, lo, hi, rel_tol,
+                     abs_tol, opt, out, grad, leaves);
+}
+
+int pg_integrate_grad(pg_context *ctx, const pg_integrand *f,
+                      const double *lo, const double *hi,
+                      const pg_options *opt, pg_result *out, double *grad,
+                      pg_leaves *leaves) {
+    if (!ctx) return PG_EINVAL;
+    if (!f || !grad || !out) {
+        ctx->err = "integrand, grad or out is NULL";
+        return PG_EINVAL;
+    }
+    pg_options o;
+    if (opt) o = *opt;
+    else pg_default_options(&o);
+    const double rt = o.rel_tol, at = o.abs_tol;
+    const int rc = run_batch(ctx, f->family, f->dim, 1, f->params, f->n_params,
+                             lo, hi, &rt, &at, &o, out, grad, leaves);
+    return rc < 0 ? rc : out->status;
 }
 
 }  // extern "C"

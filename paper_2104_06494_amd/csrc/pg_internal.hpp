@@ -112,6 +112,9 @@ struct BInst {
     int32_t relerr, paired;
     int32_t live;             // 0: ends this iteration, nothing survives
     int32_t searching;        // a threshold search runs this iteration
+    int64_t fin_base;         // its leaves of this iteration start here
+    int32_t owner;            // index of the integral in the caller's batch
+    int32_t pad2;
 };
 
 // A segment (no segment straddles an integral or the halves of a paired
@@ -156,6 +159,39 @@ hipError_t launch_batch_compact(hipStream_t st, int d, int64_t nseg,
                                 const uint32_t *offsets, double *lo_out,
                                 double *w_out, double *Vp,
                                 uint32_t *inst_out);
+// ---- parameter derivative over the final partition (pg_adjoint.hip) ------
+// Parameters as the derivative kernels take them (see pg_adjoint.hip).
+struct GParams {
+    double p[3 * PG_DIM_MAX + 2];
+};
+// Largest parameter count of a family (2d at d = PG_DIM_MAX).
+constexpr int GRAD_MAX = 2 * PG_DIM_MAX + 2;
+// Blocks per segment of the derivative kernel (the leaves are dealt out).
+constexpr int ADJ_SPLIT = 4;
+// Optional copy of the leaves: SoA [d][ld] corners and widths, the owner
+// integral of each; leaf k of an iteration goes to base + k.
+struct LeafOut {
+    double *lo, *w;
+    int32_t *owner;
+    int64_t ld, base;
+};
+int grad_nparams(int family, int d);
+bool adjoint_supported(int family, int d);
+// gpart holds GRAD_MAX x nseg x ADJ_SPLIT doubles.
+hipError_t launch_batch_adjoint(hipStream_t st, int family, int d,
+                                int64_t nseg, const BSeg *segs,
+                                const BInst *inst, const SearchState *states,
+                                const uint8_t *A_rel, const double *E,
+                                const double *lo, const double *w, int64_t ld,
+                                const GParams *gtab, const Rule &R,
+                                double *gpart, const uint32_t *offsets,
+                                const LeafOut &out);
+// git[slot * GRAD_MAX + q]: this iteration's derivative of each slot.
+hipError_t launch_batch_grad_reduce(hipStream_t st, int nslots,
+                                    const int32_t *order, const BInst *inst,
+                                    int np, const double *gpart, int64_t nseg,
+                                    double *git);
+
 // Uniform-Split of `nnew` new integrals: slot new_slots[j] gets g^d boxes
 // at inst[slot].out_start of the next list, tagged with its slot.
 hipError_t launch_batch_init(hipStream_t st, int d, int g, const double *a,
