@@ -54,6 +54,10 @@ struct pg_context {
     GParams *b_gtable = nullptr, *hb_gtable = nullptr;
     double *b_gpart = nullptr;
     double *b_git = nullptr, *hb_git = nullptr;
+    // error histograms of threshold searches (one per slot; slot 0 serves
+    // single-integral runs), zero between searches
+    uint32_t *hcnt = nullptr;
+    unsigned long long *hsum = nullptr;
     std::vector<hipEvent_t> events;
     std::string err;
     // live list left by the last pg_integrate
@@ -72,7 +76,7 @@ struct Layout {
     size_t lo[2], w[2], V, E, Vp, K, A, A2;
     size_t pv, pe, pav, pae, pmin, pmax, pcnt, off;
     size_t inst[2], b_inst, b_state, b_tot, b_table, b_order, b_new, b_segs,
-        b_cls, b_tpart, b_gtable, b_gpart, b_git;
+        b_cls, b_tpart, b_gtable, b_gpart, b_git, hcnt, hsum;
     size_t search_part, dtot, dstate, total;
     int64_t nseg;
 };
@@ -123,6 +127,8 @@ Layout layout(int dim_max, int64_t cap) {
     L.b_gtable = bump(at, sizeof(GParams) * BATCH_MAX_SLOTS);
     L.b_gpart = bump(at, sizeof(double) * GRAD_MAX * ADJ_SPLIT * L.nseg);
     L.b_git = bump(at, sizeof(double) * GRAD_MAX * BATCH_MAX_SLOTS);
+    L.hcnt = bump(at, sizeof(uint32_t) * HIST_BINS * BATCH_MAX_SLOTS);
+    L.hsum = bump(at, sizeof(unsigned long long) * HIST_BINS * BATCH_MAX_SLOTS);
     L.dtot = bump(at, sizeof(Totals));
     L.dstate = bump(at, sizeof(SearchState));
     L.total = (at + ALIGN - 1) / ALIGN * ALIGN;
@@ -305,9 +311,14 @@ int search(pg_context *ctx, int64_t n, const double *E, const uint8_t *A_rel,
     // min / max E were left in ctx->dtot by the pass that preceded the call
     HIP_OR_FAIL(ctx, launch_search_init(st, ctx->dstate, n, e_it, allowance,
                                         mem, ctx->dtot));
+    // most trials are decided from the error histogram; exact passes take
+    // over from the first one it leaves open
+    HIP_OR_FAIL(ctx, launch_search_hist(st, n, E, A_rel, ctx->dstate,
+                                        ctx->hcnt, ctx->hsum));
     int passes = 0;
-    for (int bi = 0; bi < 3 && passes < max_passes; ++bi) {
-        const int batch = std::min(SEARCH_BATCHES[bi], max_passes - passes);
+    for (int bi = -1; bi < 3 && passes < max_passes; ++bi) {
+        const int batch =
+            bi < 0 ? 0 : std::min(SEARCH_BATCHES[bi], max_passes - passes);
         for (int k = 0; k < batch; ++k)
             HIP_OR_FAIL(ctx, launch_search_pass(st, n, E, A_rel, ctx->dstate,
                                                 ctx->search_part));
@@ -457,6 +468,13 @@ int pg_context_create(int device, int dim_max, int64_t capacity,
     ctx->b_gtable = (GParams *)(b + L.b_gtable);
     ctx->b_gpart = (double *)(b + L.b_gpart);
     ctx->b_git = (double *)(b + L.b_git);
+    ctx->hcnt = (uint32_t *)(b + L.hcnt);
+    ctx->hsum = (unsigned long long *)(b + L.hsum);
+    if (hipMemset(ctx->hcnt, 0, L.hsum + sizeof(unsigned long long) * HIST_BINS *
+                                         BATCH_MAX_SLOTS - L.hcnt) != hipSuccess) {
+        pg_context_destroy(ctx);
+        return PG_EHIP;
+    }
     ctx->nseg_max = L.nseg;
     ctx->dtot = (Totals *)(b + L.dtot);
     ctx->dstate = (SearchState *)(b + L.dstate);
@@ -1149,9 +1167,14 @@ static int run_batch(pg_context *ctx, int family, int dim, int B,
                                             hipMemcpyHostToDevice, st));
             const int max_passes =
                 (THR_MAX_TRIALS + TRIAL_DEPTH - 1) / TRIAL_DEPTH;
+            HIP_OR_FAIL(ctx, launch_batch_search_hist(
+                                 st, nseg, ctx->b_segs, nslots, ctx->b_order,
+                                 ctx->b_inst, ctx->E, ctx->A, ctx->b_state,
+                                 ctx->hcnt, ctx->hsum));
             int passes = 0;
-            for (int bi = 0; bi < 3 && passes < max_passes; ++bi) {
-                const int batch = std::min(SEARCH_BATCHES[bi], max_passes - passes);
+            for (int bi = -1; bi < 3 && passes < max_passes; ++bi) {
+                const int batch = bi < 0 ? 0
+                    : std::min(SEARCH_BATCHES[bi], max_passes - passes);
                 for (int q = 0; q < batch; ++q)
                     HIP_OR_FAIL(ctx, launch_batch_search_pass(
                                          st, nseg, ctx->b_segs, nslots,

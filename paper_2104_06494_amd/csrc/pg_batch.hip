@@ -118,6 +118,31 @@ k_batch_trials(const BSeg *__restrict__ segs, int64_t nseg,
     }
 }
 
+// Error histograms of every searching slot (block per segment), then the
+// trials they decide (block per slot).
+__global__ void __launch_bounds__(LIST_THREADS)
+k_batch_hist(const BSeg *__restrict__ segs, const BInst *__restrict__ inst,
+             const SearchState *__restrict__ states,
+             const double *__restrict__ E, const uint8_t *__restrict__ A_rel,
+             uint32_t *__restrict__ cnt, unsigned long long *__restrict__ sum) {
+    const BSeg sg = segs[blockIdx.x];
+    if (!inst[sg.slot].searching || states[sg.slot].done) return;
+    hist_segment(sg.start, sg.end, E, A_rel, hist_key(states[sg.slot].mx),
+                 cnt + (size_t)sg.slot * HIST_BINS,
+                 sum + (size_t)sg.slot * HIST_BINS);
+}
+
+__global__ void __launch_bounds__(HIST_THREADS)
+k_batch_hist_walk(const int32_t *__restrict__ order,
+                  const BInst *__restrict__ inst,
+                  SearchState *__restrict__ states, uint32_t *__restrict__ cnt,
+                  unsigned long long *__restrict__ sum) {
+    const int slot = order[blockIdx.x];
+    if (!inst[slot].searching || states[slot].done) return;
+    hist_walk(states + slot, cnt + (size_t)slot * HIST_BINS,
+              sum + (size_t)slot * HIST_BINS);
+}
+
 // Adds each searching slot's segment sums in a fixed order and walks its
 // tree, one block per slot.
 __global__ void __launch_bounds__(SCAN_THREADS)
@@ -250,6 +275,22 @@ hipError_t launch_batch_search_pass(hipStream_t st, int64_t nseg,
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_batch_walk, dim3(nslots), dim3(SCAN_THREADS), 0, st,
                        order, inst, nseg, tpart, states);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_search_hist(hipStream_t st, int64_t nseg,
+                                    const BSeg *segs, int nslots,
+                                    const int32_t *order, const BInst *inst,
+                                    const double *E, const uint8_t *A_rel,
+                                    SearchState *states, uint32_t *cnt,
+                                    unsigned long long *sum) {
+    if (nseg <= 0 || nslots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_hist, dim3((unsigned)nseg), dim3(LIST_THREADS),
+                       0, st, segs, inst, states, E, A_rel, cnt, sum);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_batch_hist_walk, dim3(nslots), dim3(HIST_THREADS), 0,
+                       st, order, inst, states, cnt, sum);
     return hipGetLastError();
 }
 

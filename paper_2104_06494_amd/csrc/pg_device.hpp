@@ -224,6 +224,36 @@ __device__ inline void build_tree(const SearchState &S, double *thr) {
     }
 }
 
+// One trial of Algorithm 3 at threshold tt, given whether the memory and the
+// accuracy requirements hold there: accept, or move t (raise it when memory
+// fails, lower it when accuracy fails), counting direction changes (P_max
+// grows by 0.10 at each under memory pressure). Returns 1 when the search
+// has ended. The caller checks the trial limit first.
+__device__ inline int search_step(SearchState &st, double tt, bool mem_ok,
+                                  bool acc_ok) {
+    ++st.trials;
+    int dir;
+    if (mem_ok) {
+        if (acc_ok) {
+            st.done = 1;
+            st.ok = 1;
+            st.t_acc = tt;
+            return 1;
+        }
+        dir = -1;                               // accuracy failed: lower t
+    } else {
+        dir = +1;                               // memory failed: raise t
+    }
+    if (st.last_dir != 0 && dir != st.last_dir) {
+        ++st.dir_changes;
+        if (st.mem) st.P_max = fmin(st.P_max + 0.10, 0.95);
+        if (st.dir_changes >= THR_MAX_DIRCHG) { st.done = 1; return 1; }
+    }
+    st.last_dir = dir;
+    st.t = dir > 0 ? tt + (st.mx - tt) / 2.0 : tt - (tt - st.mn) / 2.0;
+    return 0;
+}
+
 // Walks up to TRIAL_DEPTH levels of the tree given the totals of a pass:
 // tot[m] regions stay active under node m's threshold and tot[TRIAL_M + m]
 // is the sum of their errors.
@@ -234,30 +264,194 @@ __device__ inline void walk_tree(SearchState &st, const double *tot) {
     for (int level = 0; level < TRIAL_DEPTH; ++level) {
         if (st.trials >= THR_MAX_TRIALS) { st.done = 1; return; }
         const double tt = thr[node];
-        ++st.trials;
         const double s_abar = (double)st.n - tot[node];
         const double e_abar = st.e_it - tot[TRIAL_M + node];
-        int dir;
-        if (s_abar > 0.5 * (double)st.n) {
-            if (e_abar <= st.P_max * st.allowance) {
-                st.done = 1;
-                st.ok = 1;
-                st.t_acc = tt;
-                return;
-            }
-            dir = -1;                           // accuracy failed: lower t
-        } else {
-            dir = +1;                           // memory failed: raise t
-        }
-        if (st.last_dir != 0 && dir != st.last_dir) {
-            ++st.dir_changes;
-            if (st.mem) st.P_max = fmin(st.P_max + 0.10, 0.95);
-            if (st.dir_changes >= THR_MAX_DIRCHG) { st.done = 1; return; }
-        }
-        st.last_dir = dir;
-        st.t = dir > 0 ? tt + (st.mx - tt) / 2.0 : tt - (tt - st.mn) / 2.0;
-        node = dir > 0 ? 2 * node + 1 : 2 * node + 2;
+        const bool mem_ok = s_abar > 0.5 * (double)st.n;
+        const bool acc_ok = e_abar <= st.P_max * st.allowance;
+        if (search_step(st, tt, mem_ok, acc_ok)) return;
+        node = st.last_dir > 0 ? 2 * node + 1 : 2 * node + 2;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Error histogram of the regions a threshold search works on (A_rel), so
+// that most trials are decided without a pass over the list. A bin is
+// 2^-HIST_MBITS of a binade: the key of E is its binary64 pattern shifted
+// right by HIST_SHIFT (exponent and HIST_MBITS significand bits), and bin j
+// holds key kmax - j, kmax the key of the largest E; everything further
+// down falls into the last bin. Counts are exact; a bin's sum is the exact
+// integer sum of its values' significands with HIST_DROP low bits dropped
+// (one scale per bin), so the sums are deterministic and the bounds drawn
+// from them are rigorous.
+// ---------------------------------------------------------------------------
+constexpr int HIST_MBITS = 5;
+constexpr int HIST_SHIFT = 52 - HIST_MBITS;
+constexpr int HIST_DROP = 21;                  // 32 of 53 significand bits kept
+constexpr int HIST_THREADS = 1024;
+
+__device__ inline uint64_t hist_key(double e) {
+    return __builtin_bit_cast(uint64_t, e) >> HIST_SHIFT;
+}
+
+// Adds the A_rel regions of [s0, s1) to the histogram (LDS first, then one
+// atomic per non-empty bin).
+__device__ inline void hist_segment(int64_t s0, int64_t s1,
+                                    const double *__restrict__ E,
+                                    const uint8_t *__restrict__ A_rel,
+                                    uint64_t kmax, uint32_t *__restrict__ gcnt,
+                                    unsigned long long *__restrict__ gsum) {
+    __shared__ uint32_t lc[HIST_BINS];
+    __shared__ unsigned long long ls[HIST_BINS];
+    for (int b = threadIdx.x; b < HIST_BINS; b += blockDim.x) {
+        lc[b] = 0;
+        ls[b] = 0;
+    }
+    __syncthreads();
+    for (int64_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
+        if (!A_rel[i]) continue;
+        const uint64_t bits = __builtin_bit_cast(uint64_t, E[i]);
+        const uint64_t key = bits >> HIST_SHIFT;
+        uint64_t j = key >= kmax ? 0 : kmax - key;
+        if (j > HIST_BINS - 1) j = HIST_BINS - 1;
+        atomicAdd(&lc[j], 1u);
+        if (j < HIST_BINS - 1) {
+            const uint64_t ef = (bits >> 52) & 0x7ff;
+            uint64_t m = bits & ((1ull << 52) - 1);
+            if (ef) m |= 1ull << 52;
+            atomicAdd(&ls[j], (unsigned long long)(m >> HIST_DROP));
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < HIST_BINS; b += blockDim.x) {
+        if (lc[b]) {
+            atomicAdd(&gcnt[b], lc[b]);
+            atomicAdd(&gsum[b], ls[b]);
+        }
+    }
+}
+
+// Decides as many trials as the histogram allows (HIST_THREADS threads):
+// for the bin j holding t, regions in bins above j have E > t and those
+// below have E < t, so the count and error sum of the regions kept active
+// lie in intervals; a trial is decided when both requirements come out the
+// same at both ends, with a relative margin of 1e-12 (far wider than the
+// rounding of the exact pass's sums). The first undecided trial is left to
+// the exact passes. Clears the histogram for the next search.
+__device__ inline void hist_walk(SearchState *__restrict__ gst,
+                                 uint32_t *__restrict__ gcnt,
+                                 unsigned long long *__restrict__ gsum) {
+    __shared__ double pc[HIST_BINS + 1], pl[HIST_BINS + 1], pu[HIST_BINS + 1];
+    __shared__ double csum[HIST_THREADS / 64 + 1][3];
+    constexpr int PER = HIST_BINS / HIST_THREADS;
+    const uint64_t kmax = hist_key(gst->mx);
+    double c[PER], l[PER], u[PER];
+    const int b0 = threadIdx.x * PER;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int j = b0 + q;
+        const uint32_t cnt = gcnt[j];
+        const unsigned long long sm = gsum[j];
+        gcnt[j] = 0;
+        gsum[j] = 0;
+        c[q] = (double)cnt;
+        if (j < HIST_BINS - 1) {
+            // all values of bin j share the exponent field of key kmax - j
+            const int64_t key = (int64_t)kmax - j;
+            int64_t ef = key >> HIST_MBITS;
+            if (ef < 1) ef = 1;
+            const double scale = ldexp(1.0, (int)(ef - 1075 + HIST_DROP));
+            l[q] = key < 0 ? 0.0 : (double)sm * scale;
+            u[q] = key < 0 ? 0.0 : ((double)sm + (double)cnt) * scale;
+        } else {
+            // below the lower edge of bin HIST_BINS - 2
+            const int64_t key = (int64_t)kmax - (HIST_BINS - 2);
+            const double edge = key <= 0 ? 0.0
+                : __builtin_bit_cast(double, (uint64_t)key << HIST_SHIFT);
+            l[q] = 0.0;
+            u[q] = (double)cnt * edge;
+        }
+    }
+    // exclusive prefix sums from the top bin: chunk totals, a shuffle scan
+    // within each wave, the wave totals in order (fixed order throughout)
+    double tot[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < PER; ++q) { tot[0] += c[q]; tot[1] += l[q]; tot[2] += u[q]; }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double ex[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double x = tot[a];
+        for (int o = 1; o < 64; o <<= 1) {
+            const double y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        const double before = __shfl_up(x, 1);
+        ex[a] = lane ? before : 0.0;
+        if (lane == 63) csum[wave][a] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double acc = 0.0;
+        for (int w = 0; w < HIST_THREADS / 64; ++w) {
+            const double x = csum[w][threadIdx.x];
+            csum[w][threadIdx.x] = acc;
+            acc += x;
+        }
+        csum[HIST_THREADS / 64][threadIdx.x] = acc;
+    }
+    __syncthreads();
+    {
+        double a = csum[wave][0] + ex[0], b = csum[wave][1] + ex[1],
+               d = csum[wave][2] + ex[2];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            pc[b0 + q] = a;
+            pl[b0 + q] = b;
+            pu[b0 + q] = d;
+            a += c[q];
+            b += l[q];
+            d += u[q];
+        }
+        if (threadIdx.x == HIST_THREADS - 1) {
+            pc[HIST_BINS] = a;
+            pl[HIST_BINS] = b;
+            pu[HIST_BINS] = d;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    SearchState st = *gst;
+    const double n = (double)st.n;
+    while (!st.done) {
+        if (st.trials >= THR_MAX_TRIALS) { st.done = 1; break; }
+        const double t = st.t;
+        const uint64_t kt = hist_key(t);
+        double c_lo, c_hi, s_lo, s_hi;
+        if (kt > kmax) {                       // above every error
+            c_lo = c_hi = 0.0;
+            s_lo = s_hi = 0.0;
+        } else {
+            uint64_t j = kmax - kt;
+            if (j > HIST_BINS - 1) j = HIST_BINS - 1;
+            c_lo = pc[j];
+            c_hi = pc[j + 1];
+            s_lo = pl[j] * (1.0 - 1e-12);
+            s_hi = pu[j + 1] * (1.0 + 1e-12);
+        }
+        bool mem_ok, acc_ok = false;
+        if (n - c_hi > 0.5 * n) mem_ok = true;
+        else if (!(n - c_lo > 0.5 * n)) mem_ok = false;
+        else break;                            // undecided
+        if (mem_ok) {
+            const double lim = st.P_max * st.allowance;
+            const double slack = 1e-12 * (fabs(st.e_it) + fabs(lim));
+            if (st.e_it - s_lo <= lim - slack) acc_ok = true;
+            else if (st.e_it - s_hi > lim + slack) acc_ok = false;
+            else break;                        // undecided
+        }
+        search_step(st, t, mem_ok, acc_ok);
+    }
+    *gst = st;
 }
 
 // Fixed-order sum of the 2 TRIAL_M block sums of a pass, blocks strided by

@@ -96,6 +96,9 @@ struct SearchState {
     int done, ok;
 };
 
+// Bins of the error histogram a threshold search starts from (per integral).
+constexpr int HIST_BINS = 2048;
+
 // ---- many integrals in one list (pg_batch.hip) ---------------------------
 // Each live integral of a batched run owns a slot. Its regions are
 // contiguous in the list; its survivors' children go to its own block of
@@ -146,6 +149,14 @@ hipError_t launch_batch_search_pass(hipStream_t st, int64_t nseg,
                                     const int32_t *order, const BInst *inst,
                                     const double *E, const uint8_t *A_rel,
                                     SearchState *states, double *tpart);
+// Histogram of every searching slot's errors and the trials it decides
+// (cnt / sum: HIST_BINS per slot, zero on entry and left zero).
+hipError_t launch_batch_search_hist(hipStream_t st, int64_t nseg,
+                                    const BSeg *segs, int nslots,
+                                    const int32_t *order, const BInst *inst,
+                                    const double *E, const uint8_t *A_rel,
+                                    SearchState *states, uint32_t *cnt,
+                                    unsigned long long *sum);
 hipError_t launch_batch_count(hipStream_t st, int64_t nseg, const BSeg *segs,
                               const BInst *inst, const SearchState *states,
                               const double *V, const double *E,
@@ -230,6 +241,11 @@ hipError_t launch_reduce_scan(hipStream_t st, int64_t nseg, SegPartials part,
 hipError_t launch_search_init(hipStream_t st, SearchState *S, int64_t n,
                               double e_it, double allowance, int mem,
                               const Totals *minmax);
+// The search's error histogram and the trials it decides (k_hist +
+// k_hist_walk); cnt / sum hold HIST_BINS bins, zero on entry and left zero.
+hipError_t launch_search_hist(hipStream_t st, int64_t n, const double *E,
+                              const uint8_t *A_rel, SearchState *S,
+                              uint32_t *cnt, unsigned long long *sum);
 // One pass (TRIAL_DEPTH trials) of the search: k_trials + k_trial_walk; a
 // no-op once the search has ended. blk_part holds 2 TRIAL_M x TRIAL_BLOCKS
 // doubles.

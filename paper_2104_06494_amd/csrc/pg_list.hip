@@ -73,6 +73,23 @@ __global__ void k_search_init(SearchState *__restrict__ S, int64_t n,
     *S = s;
 }
 
+// Error histogram of the A_rel regions, one block per segment, then the
+// trials it decides (see hist_walk).
+__global__ void __launch_bounds__(LIST_THREADS)
+k_hist(int64_t n, const double *__restrict__ E,
+       const uint8_t *__restrict__ A_rel, const SearchState *__restrict__ S,
+       uint32_t *__restrict__ cnt, unsigned long long *__restrict__ sum) {
+    const int64_t s0 = (int64_t)blockIdx.x * SEG;
+    const int64_t s1 = s0 + SEG < n ? s0 + SEG : n;
+    hist_segment(s0, s1, E, A_rel, hist_key(S->mx), cnt, sum);
+}
+
+__global__ void __launch_bounds__(HIST_THREADS)
+k_hist_walk(SearchState *__restrict__ S, uint32_t *__restrict__ cnt,
+            unsigned long long *__restrict__ sum) {
+    hist_walk(S, cnt, sum);
+}
+
 // One pass over the list for the TRIAL_M thresholds of the current tree.
 // Counts come from wave ballots (already wave totals, in scalar registers);
 // the error sums are reduced through LDS (each wave writes its lanes' sums
@@ -248,6 +265,19 @@ hipError_t launch_search_init(hipStream_t st, SearchState *S, int64_t n,
                               const Totals *minmax) {
     hipLaunchKernelGGL(k_search_init, dim3(1), dim3(64), 0, st, S, n, e_it,
                        allowance, mem, minmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_search_hist(hipStream_t st, int64_t n, const double *E,
+                              const uint8_t *A_rel, SearchState *S,
+                              uint32_t *cnt, unsigned long long *sum) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hist, dim3((unsigned)seg_count(n, 0)),
+                       dim3(LIST_THREADS), 0, st, n, E, A_rel, S, cnt, sum);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_hist_walk, dim3(1), dim3(HIST_THREADS), 0, st, S, cnt,
+                       sum);
     return hipGetLastError();
 }
 

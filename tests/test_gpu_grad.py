@@ -145,18 +145,18 @@ def test_adjoint_leaves_the_forward_run_unchanged(ctx):
 
 
 def test_batched_grad_equals_single_runs(ctx):
-    """Eight Gaussian parameter points, four in flight at a time."""
+    """Six Gaussian parameter points, three in flight at a time."""
     _say("grad-batch-vs-single")
     import paper_2104_06494_amd as pg
-    wl = W.gaussian_grad_d6(B=8)
-    wl.rel_tol[:] = 1e-6
-    wl.max_regions = 1 << 18
-    c = pg.Context(capacity=4 << 18, dim_max=6)
+    wl = W.gaussian_grad_d6(B=6)
+    wl.rel_tol[:] = 1e-4
+    wl.max_regions = 1 << 16
+    c = pg.Context(capacity=3 << 16, dim_max=6)
     res, G, L = c.integrate_batch_workload(wl, grad=True, leaves_capacity=1 << 22)
     owner = L["owner"].cpu().numpy()
     lo, w = L["lo"].cpu().numpy(), L["w"].cpu().numpy()
     for b in range(wl.B):
-        r1, g1, _ = c.integrate_grad("gaussian", 6, wl.params[b], rel_tol=1e-6,
+        r1, g1, _ = c.integrate_grad("gaussian", 6, wl.params[b], rel_tol=1e-4,
                                      init_splits=2, max_regions=wl.max_regions)
         assert (r1.status, r1.iterations, r1.regions_evaluated) == \
             (res[b].status, res[b].iterations, res[b].regions_evaluated)
