@@ -38,7 +38,7 @@ F_GAUSSIAN_D5 = 47.0
 # HBM bytes per evaluate launch of this workload from FETCH_SIZE / WRITE_SIZE
 # (scaled by a plain copy), valid only for the kernel source they were taken
 # on (first 16 hex digits of its sha256); reported as null otherwise.
-EVAL_TRAFFIC = {"bytes_per_launch": 37569203.0, "kernel_sha256": "c18f8b134e26a73c",
+EVAL_TRAFFIC = {"bytes_per_launch": 37796101.0, "kernel_sha256": "d059381e737079ed",
                 "profile": "profiles/evaluate_gaussian_d5_counters.txt"}
 # MI355X FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz.
 PEAK_FP64_TFLOPS = 78.6

@@ -6,10 +6,13 @@
 // (one axis: +-lambda2, +-lambda3; one pair of axes: four sign choices of
 // lambda4; four sign vectors of lambda5); W waves of a block share the same
 // 64 regions and take every W-th unit, so small lists still fill the chip.
-// The unit index is wave-uniform: which coordinates move, and with what
-// sign, is decided in scalar registers, and every lane builds its point with
-// one FMA per coordinate, x_k = c_k + s_k (lambda h_k), s_k in {-1, 0, 1},
-// which rounds exactly like c_k + s_k * (lambda * h_k).
+// Axis and pair units are unrolled with the moving axes as compile-time
+// indices: a point differs from the centre only in those coordinates, each
+// one FMA, x_k = c_k + s_k (lambda h_k), which rounds exactly like
+// c_k + s_k * (lambda * h_k); the untouched coordinates stay the centre's
+// registers, and the integrand's arithmetic on them is shared by the four
+// points of a unit where the compiler can see it is the same. Which unit a
+// wave takes is decided in scalar registers (wave-uniform branches).
 #include "pg_internal.hpp"
 
 #include <hip/hip_runtime.h>
@@ -77,7 +80,6 @@ k_evaluate(const FParams P, const Rule R, int64_t n,
            const FParams *__restrict__ table) {
     constexpr int NPAIR = D * (D - 1) / 2;
     constexpr int N5 = (1 << D) / 4;         // units of four orbit-5 points
-    constexpr int U = D + NPAIR + N5;
     extern __shared__ double lds[];          // Dbuf[D][64], part[W][5][64]
 
     const int lane = threadIdx.x & 63;
@@ -111,46 +113,55 @@ k_evaluate(const FParams P, const Rule R, int64_t n,
     double S2 = 0.0, S3 = 0.0, S4 = 0.0, S5 = 0.0, nmax = 0.0;
     double *Dbuf = lds;
 
-    for (int u = wave; u < U; u += W) {
-        double x[D];
-        if (u < D) {
-            // orbits 2 and 3 along axis i, and its fourth difference
-            const int i = u;
-            double f[4];
+    // axis units: the axis is a compile-time index, so only the moving
+    // coordinate is recomputed (unit u = i goes to wave u mod W)
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        if (i % W != wave) continue;
+        double f[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            double x[D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) x[k] = c[k];
+            const double lam = q < 2 ? R.lam2 : R.lam3;
+            x[i] = fma((q & 1) ? -1.0 : 1.0, lam * h[i], c[i]);
+            f[q] = integrand<FAM, D>(x, PP);
+        }
+        const double P2 = f[0] + f[1], P3 = f[2] + f[3];
+        S2 += P2;
+        S3 += P3;
+        Dbuf[i * 64 + lane] = fabs((P2 - 2.0 * fc) - (P3 - 2.0 * fc) / 7.0);
+        const double nm = (fabs(f[0]) + fabs(f[1])) +
+                          (fabs(f[2]) + fabs(f[3])) / 7.0 +
+                          (12.0 / 7.0) * fabs(fc);
+        nmax = fmax(nmax, nm);
+    }
+    // pair units, pairs in row order, unit u = D + pair index
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+#pragma unroll
+        for (int j = i + 1; j < D; ++j) {
+            const int u = D + i * (2 * D - i - 1) / 2 + (j - i - 1);
+            if (u % W != wave) continue;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const double lam = q < 2 ? R.lam2 : R.lam3;
-                const double sg = (q & 1) ? -1.0 : 1.0;
+                double x[D];
 #pragma unroll
-                for (int k = 0; k < D; ++k)
-                    x[k] = fma(k == i ? sg : 0.0, lam * h[k], c[k]);
-                f[q] = integrand<FAM, D>(x, PP);
-            }
-            const double P2 = f[0] + f[1], P3 = f[2] + f[3];
-            S2 += P2;
-            S3 += P3;
-            Dbuf[i * 64 + lane] = fabs((P2 - 2.0 * fc) - (P3 - 2.0 * fc) / 7.0);
-            const double nm = (fabs(f[0]) + fabs(f[1])) +
-                              (fabs(f[2]) + fabs(f[3])) / 7.0 +
-                              (12.0 / 7.0) * fabs(fc);
-            nmax = fmax(nmax, nm);
-        } else if (u < D + NPAIR) {
-            // orbit 4: pair (i, j) with i < j, pairs in row order
-            int i = 0, rem = u - D;
-            while (rem >= D - 1 - i) { rem -= D - 1 - i; ++i; }
-            const int j = i + 1 + rem;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const double si = (q & 2) ? -1.0 : 1.0;
-                const double sj = (q & 1) ? -1.0 : 1.0;
-#pragma unroll
-                for (int k = 0; k < D; ++k)
-                    x[k] = fma(k == i ? si : (k == j ? sj : 0.0), l4[k], c[k]);
+                for (int k = 0; k < D; ++k) x[k] = c[k];
+                x[i] = fma((q & 2) ? -1.0 : 1.0, l4[i], c[i]);
+                x[j] = fma((q & 1) ? -1.0 : 1.0, l4[j], c[j]);
                 S4 += integrand<FAM, D>(x, PP);
             }
-        } else {
-            // orbit 5: sign vectors 4m..4m+3, bit k set = minus on axis k
-            const int m = u - D - NPAIR;
+        }
+    }
+    // vertex units
+    {
+        int u0 = D + NPAIR;
+        int m = wave - (u0 % W);
+        if (m < 0) m += W;
+        for (; m < N5; m += W) {
+            double x[D];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int b = 4 * m + q;
