@@ -28,25 +28,35 @@ namespace {
 // operations, and more resident waves hide their latency.
 constexpr int ADJ_WAVES_PER_SIMD = 2;
 
-// Parameters in the number the derivative kernels read them:
-//   product peak: p[k] = a_k^-2, p[d+k] = u_k, p[2d+k] = 2 a_k^-3
-//   gaussian:     p[k] = a_k,    p[d+k] = u_k
-//   oscillatory:  p[k] = a_k,    p[d]   = 2 pi u_1
-//   corner peak:  p[k] = a_k
+// Parameters as the derivative kernels read them: p as FParams would hold
+// them for the integrand, and gs[q] the constant factor of parameter q's
+// derivative (see point_grad):
+//   product peak: p[k] = a_k^-2, p[d+k] = u_k;  gs = 2 a_k^-3, 2
+//   gaussian:     p[k] = a_k,    p[d+k] = u_k;  gs = -2 a_k, 2 a_k^2
+//   oscillatory:  p[k] = a_k,    p[d] = 2 pi u_1;  gs = -1, -2 pi
+//   corner peak:  p[k] = a_k;  gs = -(d+1)
 template <int FAM, int D>
 constexpr int n_grad() {
     return (FAM == PG_PRODUCT_PEAK || FAM == PG_GAUSSIAN) ? 2 * D
            : FAM == PG_OSCILLATORY ? D + 1 : D;
 }
 
-// g += wgt * df/dtheta at x (derivatives of the integrand families with
-// respect to their user parameters).
+// g += wgt * (df/dtheta at x) / gs: each family's parameter derivatives
+// share a constant factor per parameter, applied once per integral after
+// the sums (k_batch_grad_reduce):
+//   gaussian  f = exp(-sum a^2 t^2), t = x - u:
+//             df/da_k = -2 a_k (t_k^2 f),   df/du_k = 2 a_k^2 (t_k f)
+//   product   f = prod r_k, r_k = 1 / (a_k^-2 + t_k^2):
+//             df/da_k = 2 a_k^-3 (f r_k),   df/du_k = 2 (f t_k r_k)
+//   oscillatory f = cos(phi), phi = 2 pi u_1 + sum a x:
+//             df/da_k = -(x_k sin phi),     df/du_1 = -2 pi (sin phi)
+//   corner    f = s^-(d+1), s = 1 + sum a x:
+//             df/da_k = -(d+1) (x_k s^-(d+2))
 template <int FAM, int D>
 __device__ __forceinline__ void point_grad(const double (&x)[D],
                                            const GParams &P, double wgt,
                                            double *g) {
     if constexpr (FAM == PG_GAUSSIAN) {
-        // f = exp(-sum a^2 t^2), t = x - u: d/da = -2 a t^2 f, d/du = 2 a^2 t f
         double t[D], s = 0.0;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
@@ -57,13 +67,11 @@ __device__ __forceinline__ void point_grad(const double (&x)[D],
         const double wf = wgt * exp(-s);
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            const double at = P.p[k] * t[k];
-            g[k] = fma(-2.0 * at * t[k], wf, g[k]);
-            g[D + k] = fma(2.0 * at * P.p[k], wf, g[D + k]);
+            const double wt = wf * t[k];
+            g[D + k] += wt;
+            g[k] = fma(wt, t[k], g[k]);
         }
     } else if constexpr (FAM == PG_PRODUCT_PEAK) {
-        // f = prod r_k, r_k = 1 / (a^-2 + t^2): d/da = f (2 a^-3) r_k,
-        // d/du = f 2 t r_k
         double t[D], r[D], f = 1.0;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
@@ -75,20 +83,18 @@ __device__ __forceinline__ void point_grad(const double (&x)[D],
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             const double wr = wf * r[k];
-            g[k] = fma(P.p[2 * D + k], wr, g[k]);
-            g[D + k] = fma(2.0 * t[k], wr, g[D + k]);
+            g[k] += wr;
+            g[D + k] = fma(wr, t[k], g[D + k]);
         }
     } else if constexpr (FAM == PG_OSCILLATORY) {
-        // f = cos(phi), phi = 2 pi u_1 + sum a x: d/da = -x sin, d/du_1 = -2 pi sin
         double phi = P.p[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) phi = fma(P.p[k], x[k], phi);
         const double ws = wgt * sin(phi);
 #pragma unroll
-        for (int k = 0; k < D; ++k) g[k] = fma(-x[k], ws, g[k]);
-        g[D] = fma(-2.0 * M_PI, ws, g[D]);
+        for (int k = 0; k < D; ++k) g[k] = fma(x[k], ws, g[k]);
+        g[D] += ws;
     } else {
-        // f = s^-(d+1), s = 1 + sum a x: d/da = -(d+1) x s^-(d+2)
         double s = 1.0;
 #pragma unroll
         for (int k = 0; k < D; ++k) s = fma(P.p[k], x[k], s);
@@ -96,64 +102,61 @@ __device__ __forceinline__ void point_grad(const double (&x)[D],
         double f = r;
 #pragma unroll
         for (int k = 1; k < D + 2; ++k) f *= r;
-        const double wf = -(double)(D + 1) * wgt * f;
+        const double wf = wgt * f;
 #pragma unroll
         for (int k = 0; k < D; ++k) g[k] = fma(x[k], wf, g[k]);
     }
 }
 
-// Derivative of one region's rule value without the volume factor. The
-// points are walked in the evaluation's work units of four (one axis:
-// +-lambda2, +-lambda3; one pair of axes: the four sign choices of lambda4;
-// four sign vectors of lambda5) plus the centre; the unit index is the same
-// on every lane, so signs are chosen in scalar registers and each
-// coordinate is one FMA, x_k = c_k + s_k (lambda h_k), rounded as the
-// evaluation rounds it.
+// Derivative of one region's rule value without the volume factor, over
+// the points of the degree-7 rule: the centre; the axis units (+-lambda2,
+// +-lambda3 on one axis) and pair units (the four sign choices of lambda4
+// on two axes), unrolled with the moving axes as compile-time indices so a
+// point moves one or two coordinates off the centre with one FMA each,
+// x_k = c_k + s_k (lambda h_k) as the evaluation rounds it; and the 2^d
+// vertices at lambda5, four per loop step.
 template <int FAM, int D>
 __device__ __forceinline__ void region_grad(const double (&c)[D],
                                             const double (&h)[D],
                                             const GParams &P, const Rule &R,
                                             double *g) {
-    constexpr int NPAIR = D * (D - 1) / 2;
-    constexpr int N5 = (1 << D) / 4;
-    constexpr int U = D + NPAIR + N5;
     point_grad<FAM, D>(c, P, R.w7[0], g);
-    for (int u = 0; u < U; ++u) {
-        double x[D];
-        if (u < D) {
 #pragma unroll
+    for (int i = 0; i < D; ++i) {
+#pragma unroll 1
+        for (int q = 0; q < 4; ++q) {
+            double x[D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) x[k] = c[k];
+            const double lam = q < 2 ? R.lam2 : R.lam3;
+            x[i] = fma((q & 1) ? -1.0 : 1.0, lam * h[i], c[i]);
+            point_grad<FAM, D>(x, P, q < 2 ? R.w7[1] : R.w7[2], g);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+#pragma unroll
+        for (int j = i + 1; j < D; ++j) {
+#pragma unroll 1
             for (int q = 0; q < 4; ++q) {
-                const double lam = q < 2 ? R.lam2 : R.lam3;
-                const double sg = (q & 1) ? -1.0 : 1.0;
+                double x[D];
 #pragma unroll
-                for (int k = 0; k < D; ++k)
-                    x[k] = fma(k == u ? sg : 0.0, lam * h[k], c[k]);
-                point_grad<FAM, D>(x, P, q < 2 ? R.w7[1] : R.w7[2], g);
-            }
-        } else if (u < D + NPAIR) {
-            int i = 0, rem = u - D;
-            while (rem >= D - 1 - i) { rem -= D - 1 - i; ++i; }
-            const int j = i + 1 + rem;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const double si = (q & 2) ? -1.0 : 1.0;
-                const double sj = (q & 1) ? -1.0 : 1.0;
-#pragma unroll
-                for (int k = 0; k < D; ++k)
-                    x[k] = fma(k == i ? si : (k == j ? sj : 0.0), R.lam4 * h[k],
-                               c[k]);
+                for (int k = 0; k < D; ++k) x[k] = c[k];
+                x[i] = fma((q & 2) ? -1.0 : 1.0, R.lam4 * h[i], c[i]);
+                x[j] = fma((q & 1) ? -1.0 : 1.0, R.lam4 * h[j], c[j]);
                 point_grad<FAM, D>(x, P, R.w7[3], g);
             }
-        } else {
-            const int m = u - D - NPAIR;
+        }
+    }
+    for (int m = 0; m < (1 << D) / 4; ++m) {
+#pragma unroll 2
+        for (int q = 0; q < 4; ++q) {
+            const int b = 4 * m + q;
+            double x[D];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int b = 4 * m + q;
-#pragma unroll
-                for (int k = 0; k < D; ++k)
-                    x[k] = fma(((b >> k) & 1) ? -1.0 : 1.0, R.lam5 * h[k], c[k]);
-                point_grad<FAM, D>(x, P, R.w7[4], g);
-            }
+            for (int k = 0; k < D; ++k)
+                x[k] = fma(((b >> k) & 1) ? -1.0 : 1.0, R.lam5 * h[k], c[k]);
+            point_grad<FAM, D>(x, P, R.w7[4], g);
         }
     }
 }
@@ -258,10 +261,12 @@ k_batch_adjoint(const BSeg *__restrict__ segs, const BInst *__restrict__ inst,
     }
 }
 
-// Per integral: its columns of gpart added in a fixed order.
+// Per integral: its columns of gpart added in a fixed order, times the
+// parameter's constant factor.
 __global__ void __launch_bounds__(LIST_THREADS)
 k_batch_grad_reduce(const int32_t *__restrict__ order,
-                    const BInst *__restrict__ inst, int np,
+                    const BInst *__restrict__ inst,
+                    const GParams *__restrict__ gtab, int np,
                     const double *__restrict__ gpart, int64_t ncol,
                     double *__restrict__ git) {
     __shared__ double red[LIST_THREADS];
@@ -278,7 +283,8 @@ k_batch_grad_reduce(const int32_t *__restrict__ order,
             if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
             __syncthreads();
         }
-        if (threadIdx.x == 0) git[(int64_t)slot * GRAD_MAX + q] = red[0];
+        if (threadIdx.x == 0)
+            git[(int64_t)slot * GRAD_MAX + q] = red[0] * gtab[slot].gs[q];
         __syncthreads();
     }
 }
@@ -341,11 +347,12 @@ hipError_t launch_batch_adjoint(hipStream_t st, int family, int d,
 
 hipError_t launch_batch_grad_reduce(hipStream_t st, int nslots,
                                     const int32_t *order, const BInst *inst,
-                                    int np, const double *gpart, int64_t nseg,
+                                    const GParams *gtab, int np,
+                                    const double *gpart, int64_t nseg,
                                     double *git) {
     if (nslots <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_batch_grad_reduce, dim3(nslots), dim3(LIST_THREADS), 0,
-                       st, order, inst, np, gpart, nseg * ADJ_SPLIT, git);
+                       st, order, inst, gtab, np, gpart, nseg * ADJ_SPLIT, git);
     return hipGetLastError();
 }
 

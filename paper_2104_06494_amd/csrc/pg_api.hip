@@ -244,18 +244,31 @@ void make_gparams(int family, int d, const double *p, GParams *G) {
         for (int k = 0; k < d; ++k) {
             G->p[k] = 1.0 / (p[k] * p[k]);
             G->p[d + k] = p[d + k];
-            G->p[2 * d + k] = 2.0 / (p[k] * p[k] * p[k]);
+            G->gs[k] = 2.0 / (p[k] * p[k] * p[k]);
+            G->gs[d + k] = 2.0;
         }
         break;
     case PG_GAUSSIAN:
-        for (int k = 0; k < 2 * d; ++k) G->p[k] = p[k];
+        for (int k = 0; k < d; ++k) {
+            G->p[k] = p[k];
+            G->p[d + k] = p[d + k];
+            G->gs[k] = -2.0 * p[k];
+            G->gs[d + k] = 2.0 * p[k] * p[k];
+        }
         break;
     case PG_OSCILLATORY:
-        for (int k = 0; k < d; ++k) G->p[k] = p[k];
+        for (int k = 0; k < d; ++k) {
+            G->p[k] = p[k];
+            G->gs[k] = -1.0;
+        }
         G->p[d] = 2.0 * M_PI * p[d];
+        G->gs[d] = -2.0 * M_PI;
         break;
     default:
-        for (int k = 0; k < d; ++k) G->p[k] = p[k];
+        for (int k = 0; k < d; ++k) {
+            G->p[k] = p[k];
+            G->gs[k] = -(double)(d + 1);
+        }
         break;
     }
 }
@@ -1277,7 +1290,8 @@ static int run_batch(pg_context *ctx, int family, int dim, int B,
                                  ctx->b_gpart, ctx->off, lout));
             HIP_OR_FAIL(ctx, launch_batch_grad_reduce(
                                  st, nslots, ctx->b_order, ctx->b_inst,
-                                 n_params, ctx->b_gpart, nseg, ctx->b_git));
+                                 ctx->b_gtable, n_params, ctx->b_gpart, nseg,
+                                 ctx->b_git));
             HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->hb_git, ctx->b_git,
                                             sizeof(double) * GRAD_MAX * K,
                                             hipMemcpyDeviceToHost, st));

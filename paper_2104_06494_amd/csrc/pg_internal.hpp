@@ -171,12 +171,14 @@ hipError_t launch_batch_compact(hipStream_t st, int d, int64_t nseg,
                                 double *w_out, double *Vp,
                                 uint32_t *inst_out);
 // ---- parameter derivative over the final partition (pg_adjoint.hip) ------
-// Parameters as the derivative kernels take them (see pg_adjoint.hip).
-struct GParams {
-    double p[3 * PG_DIM_MAX + 2];
-};
 // Largest parameter count of a family (2d at d = PG_DIM_MAX).
 constexpr int GRAD_MAX = 2 * PG_DIM_MAX + 2;
+// Parameters as the derivative kernels take them: the integrand's (as in
+// FParams) and each parameter's constant derivative factor (pg_adjoint.hip).
+struct GParams {
+    double p[2 * PG_DIM_MAX + 2];
+    double gs[GRAD_MAX];
+};
 // Blocks per segment of the derivative kernel (the leaves are dealt out).
 constexpr int ADJ_SPLIT = 4;
 // Optional copy of the leaves: SoA [d][ld] corners and widths, the owner
@@ -200,7 +202,8 @@ hipError_t launch_batch_adjoint(hipStream_t st, int family, int d,
 // git[slot * GRAD_MAX + q]: this iteration's derivative of each slot.
 hipError_t launch_batch_grad_reduce(hipStream_t st, int nslots,
                                     const int32_t *order, const BInst *inst,
-                                    int np, const double *gpart, int64_t nseg,
+                                    const GParams *gtab, int np,
+                                    const double *gpart, int64_t nseg,
                                     double *git);
 
 // Uniform-Split of `nnew` new integrals: slot new_slots[j] gets g^d boxes
