@@ -18,7 +18,8 @@ _LIB_PATH = os.environ.get("PAGANI_ORACLE_LIB",
 _lib = None
 
 FAMILY_ID = {"product_peak": 0, "gaussian": 1, "oscillatory": 2,
-             "corner_peak": 3, "monomial": 4}
+             "corner_peak": 3, "monomial": 4, "c0": 5, "discontinuous": 6,
+             "box": 7}
 
 STATUS = {0: "OK", 1: "MAX_ITERS", 2: "MEMORY_EXHAUSTED", 3: "NO_ACTIVE"}
 

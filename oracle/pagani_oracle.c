@@ -44,14 +44,16 @@
 #define OR_DMAX 16
 
 enum { OR_PRODUCT_PEAK = 0, OR_GAUSSIAN = 1, OR_OSCILLATORY = 2,
-       OR_CORNER_PEAK = 3, OR_MONOMIAL = 4 };
+       OR_CORNER_PEAK = 3, OR_MONOMIAL = 4, OR_C0 = 5, OR_DISCONTINUOUS = 6,
+       OR_BOX = 7 };
 
 enum { OR_OK = 0, OR_MAX_ITERS = 1, OR_MEMORY_EXHAUSTED = 2,
        OR_NO_ACTIVE = 3, OR_EINVAL = -1, OR_ENOMEM = -2, OR_EREPLAY = -5 };
 
 /* ------------------------------------------------------------------------
- * Integrands (Section 4.1 uses members of these families; the workloads
- * draw their parameters at random).
+ * Integrands (Section 4.1 uses members of these families, and the box
+ * integrals; the workloads draw their parameters at random or take the
+ * paper's fixed ones).
  * ---------------------------------------------------------------------- */
 double oracle_f(int family, int d, const double *p, const double *x)
 {
@@ -90,6 +92,23 @@ double oracle_f(int family, int d, const double *p, const double *x)
                 r = r * x[i];
         }
         return r;
+    case OR_C0:                      /* exp(-sum a |x - u|) */
+        s = 0.0;
+        for (i = 0; i < d; i++)
+            s = s + p[i] * fabs(x[i] - p[d + i]);
+        return exp(-s);
+    case OR_DISCONTINUOUS:           /* exp(sum a x) if every x_i < c_i */
+        s = 0.0;
+        for (i = 0; i < d; i++) {
+            if (!(x[i] < p[d + i])) return 0.0;
+            s = s + p[i] * x[i];
+        }
+        return exp(s);
+    case OR_BOX:                     /* (sum x^2)^p */
+        s = 0.0;
+        for (i = 0; i < d; i++)
+            s = s + x[i] * x[i];
+        return pow(s, p[0]);
     default:
         return NAN;
     }

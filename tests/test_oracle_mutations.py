@@ -62,13 +62,24 @@ GRAD_MUTANTS = {
                                 "        /* finished regions dropped */"),
 }
 
+# mistakes in the extra families of the paper's suite
+SUITE_MUTANTS = {
+    "c0_no_abs": ("s = s + p[i] * fabs(x[i] - p[d + i]);",
+                  "s = s + p[i] * (x[i] - p[d + i]);"),
+    "discontinuous_cutoff_param": ("if (!(x[i] < p[d + i])) return 0.0;",
+                                   "if (!(x[i] < p[i])) return 0.0;"),
+    "box_not_squared": ("            s = s + x[i] * x[i];\n        return pow(s, p[0]);",
+                        "            s = s + x[i];\n        return pow(s, p[0]);"),
+}
+
 CASES = [(n, "test_oracle_pins.py") for n in sorted(MUTANTS)] + \
-        [(n, "test_oracle_grad_pins.py") for n in sorted(GRAD_MUTANTS)]
+        [(n, "test_oracle_grad_pins.py") for n in sorted(GRAD_MUTANTS)] + \
+        [(n, "test_oracle_suite_pins.py") for n in sorted(SUITE_MUTANTS)]
 
 
 @pytest.mark.parametrize("name,pins", CASES, ids=[c[0] for c in CASES])
 def test_mutant_is_caught(name, pins, tmp_path):
-    old, new = {**MUTANTS, **GRAD_MUTANTS}[name]
+    old, new = {**MUTANTS, **GRAD_MUTANTS, **SUITE_MUTANTS}[name]
     src = open(SRC).read()
     assert src.count(old) == 1, f"mutation anchor not unique: {name}"
     mut = tmp_path / "mutant.c"

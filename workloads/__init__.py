@@ -16,6 +16,9 @@ paper's own test functions (Section 4.1) belong to the same Genz families:
 * ``oscillatory``   f(x) = cos(2 pi u_1 + sum_i a_i x_i)
 * ``corner_peak``   f(x) = (1 + sum_i a_i x_i)^-(d+1)
 * ``monomial``      f(x) = prod_i x_i^alpha_i   (test family, integer alpha)
+* ``c0``            f(x) = exp(-sum_i a_i |x_i - u_i|)            (Genz C0)
+* ``discontinuous`` f(x) = exp(sum_i a_i x_i) if x_i < c_i for all i, else 0
+* ``box``           f(x) = (sum_i x_i^2)^p                        (box integrals)
 
 Parameter vector layout per family (``params``):
 
@@ -23,6 +26,9 @@ Parameter vector layout per family (``params``):
 * oscillatory:            ``[a_1..a_d, u_1]``        (d+1 values)
 * corner_peak:            ``[a_1..a_d]``             (d values)
 * monomial:               ``[alpha_1..alpha_d]``     (d values, integers)
+* c0:                     ``[a_1..a_d, u_1..u_d]``   (2d values)
+* discontinuous:          ``[a_1..a_d, c_1..c_d]``   (2d values)
+* box:                    ``[p]``                    (1 value)
 """
 from __future__ import annotations
 
@@ -35,13 +41,18 @@ FAMILIES = {
     "oscillatory": 2,
     "corner_peak": 3,
     "monomial": 4,
+    "c0": 5,
+    "discontinuous": 6,
+    "box": 7,
 }
 
 
 def n_params(family: str, d: int) -> int:
     """Length of the parameter vector of ``family`` in dimension ``d``."""
-    if family in ("product_peak", "gaussian"):
+    if family in ("product_peak", "gaussian", "c0", "discontinuous"):
         return 2 * d
+    if family == "box":
+        return 1
     if family == "oscillatory":
         return d + 1
     if family in ("corner_peak", "monomial"):
@@ -144,6 +155,48 @@ def oscillatory_d8(relerr_filter: int = 1) -> Workload:
     return Workload("oscillatory_d8", "oscillatory", 8,
                     oscillatory_params(8, seed=3), rel_tol=1e-5,
                     init_splits=2, relerr_filter=relerr_filter)
+
+
+# --------------------------------------------------------------------------
+# The paper's own test suite (Section 4.1): fixed parameters, unit cube.
+# Each entry: name, family, d, params, initial splits per axis.
+# --------------------------------------------------------------------------
+
+def _idx(d):
+    return np.arange(1, d + 1, dtype=np.float64)
+
+
+def paper_suite():
+    """f1..f8 of Section 4.1 in the dimensions the paper reports (8-d f1,
+    f3, f4, f5, f7, f8; 5-d f4; 6-d f6 and f2; 3-d f3), as (name, Workload)
+    with rel_tol 1e-3 (the sweep sets its own tolerances). Initial grids:
+    2^d splits (the halving planes fall on the kinks of f5 and on the
+    cut-off of f6 at 1/2), 4^3 for 3-d and 4^5 for 5-d."""
+    half = lambda d: np.full(d, 0.5)
+    S = []
+    d = 8
+    S.append(("f1_d8", "oscillatory", d, np.concatenate([_idx(d), [0.0]]), 2, 0))
+    S.append(("f2_d6", "product_peak", 6, np.concatenate([np.full(6, 50.0), half(6)]), 2, 1))
+    S.append(("f3_d3", "corner_peak", 3, _idx(3), 4, 1))
+    S.append(("f3_d8", "corner_peak", d, _idx(d), 2, 1))
+    S.append(("f4_d5", "gaussian", 5, np.concatenate([np.full(5, 25.0), half(5)]), 4, 1))
+    S.append(("f4_d8", "gaussian", d, np.concatenate([np.full(d, 25.0), half(d)]), 2, 1))
+    S.append(("f5_d8", "c0", d, np.concatenate([np.full(d, 10.0), half(d)]), 2, 1))
+    S.append(("f6_d6", "discontinuous", 6,
+              np.concatenate([_idx(6) + 4.0, (3.0 + _idx(6)) / 10.0]), 2, 1))
+    S.append(("f7_d8", "box", d, np.array([11.0]), 2, 1))
+    S.append(("f8_d8", "box", d, np.array([7.5]), 2, 1))
+    out = []
+    for name, fam, dd, par, g, relerr in S:
+        out.append((name, Workload(name, fam, dd, par, rel_tol=1e-3, init_splits=g,
+                                   relerr_filter=relerr)))
+    return out
+
+
+def paper_tolerances():
+    """The sweep of Section 4: 1e-3 down to 1.024e-10, each a fifth of the
+    one before."""
+    return [1e-3 * 0.2 ** k for k in range(11)]
 
 
 @dataclass

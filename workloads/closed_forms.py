@@ -109,6 +109,74 @@ def monomial(alpha, lo, hi) -> Fraction:
     return r
 
 
+def c0(params, d, lo=None, hi=None) -> float:
+    """prod_i int exp(-a_i |x - u_i|) dx over [lo_i, hi_i]:
+    (2 - e^{-a(u - lo)} - e^{-a(hi - u)}) / a for lo <= u <= hi."""
+    a = [mp.mpf(float(x)) for x in params[:d]]
+    u = [mp.mpf(float(x)) for x in params[d:2 * d]]
+    L, H = _bounds(d, lo, hi)
+    r = mp.mpf(1)
+    for i in range(d):
+        if not (L[i] <= u[i] <= H[i]):
+            raise ValueError("c0 closed form needs lo <= u <= hi")
+        r *= (2 - mp.exp(-a[i] * (u[i] - L[i])) - mp.exp(-a[i] * (H[i] - u[i]))) / a[i]
+    return float(r)
+
+
+def discontinuous(params, d, lo=None, hi=None) -> float:
+    """prod_i int_{lo_i}^{min(c_i, hi_i)} e^{a_i x} dx (zero if c_i <= lo_i)."""
+    a = [mp.mpf(float(x)) for x in params[:d]]
+    c = [mp.mpf(float(x)) for x in params[d:2 * d]]
+    L, H = _bounds(d, lo, hi)
+    r = mp.mpf(1)
+    for i in range(d):
+        top = min(c[i], H[i])
+        if top <= L[i]:
+            return 0.0
+        r *= (top - L[i]) if a[i] == 0 else (mp.exp(a[i] * top) - mp.exp(a[i] * L[i])) / a[i]
+    return float(r)
+
+
+def _square_sum_moments(p: int, d: int):
+    """E[S^k], k = 0..p, S the sum of d squares of independent U(0,1):
+    exact rationals, adding one axis at a time by the binomial theorem
+    (E[X^(2j)] = 1/(2j+1))."""
+    from math import comb
+    M = [Fraction(1 if k == 0 else 0) for k in range(p + 1)]
+    for _ in range(d):
+        M = [sum(Fraction(comb(k, j)) * M[j] / (2 * (k - j) + 1) for j in range(k + 1))
+             for k in range(p + 1)]
+    return M
+
+
+def box(params, d) -> float:
+    """int_{[0,1]^d} (sum x_i^2)^p dx. Integer p: the exact rational moment.
+    Otherwise E[S^p] from the Laplace-transform identity, for n < p < n+1,
+    S^p = (1/Gamma(-p)) int_0^inf (e^{-tS} - sum_{k<=n} (-tS)^k/k!) t^{-p-1} dt,
+    with E[e^{-tS}] = (sqrt(pi)/(2 sqrt t) erf(sqrt t))^d: the part over
+    [0, 1/2] termwise from the moment series, the rest by quadrature, at
+    40 significant digits."""
+    pw = float(params[0])
+    if pw == int(pw) and pw >= 0:
+        return float(_square_sum_moments(int(pw), d)[int(pw)])
+    with mp.workdps(40):
+        alpha = mp.mpf(pw)
+        n = int(mp.floor(alpha))
+        K = 90
+        mk = [mp.mpf(x.numerator) / x.denominator for x in _square_sum_moments(K, d)]
+        t0 = mp.mpf("0.5")
+        head = mp.fsum((-1) ** k * mk[k] / mp.factorial(k) * t0 ** (k - alpha) / (k - alpha)
+                       for k in range(n + 1, K + 1))
+
+        def integrand(t):
+            m = (mp.sqrt(mp.pi) / (2 * mp.sqrt(t)) * mp.erf(mp.sqrt(t))) ** d
+            poly = mp.fsum((-t) ** k * mk[k] / mp.factorial(k) for k in range(n + 1))
+            return (m - poly) * t ** (-alpha - 1)
+
+        tail = mp.quad(integrand, [t0, 2, 10, 100, mp.inf])
+        return float((head + tail) / mp.gamma(-alpha))
+
+
 def exact(family: str, params, d, lo=None, hi=None) -> float:
     if family == "product_peak":
         return product_peak(params, d, lo, hi)
@@ -124,6 +192,14 @@ def exact(family: str, params, d, lo=None, hi=None) -> float:
         lo = np.zeros(d) if lo is None else lo
         hi = np.ones(d) if hi is None else hi
         return float(monomial(params, lo, hi))
+    if family == "c0":
+        return c0(params, d, lo, hi)
+    if family == "discontinuous":
+        return discontinuous(params, d, lo, hi)
+    if family == "box":
+        if lo is not None and (np.any(np.asarray(lo) != 0) or np.any(np.asarray(hi) != 1)):
+            raise ValueError("box closed form is for the unit cube")
+        return box(params, d)
     raise ValueError(family)
 
 
