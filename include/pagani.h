@@ -24,7 +24,11 @@
  *      PG_OSCILLATORY   cos(2 pi u_1 + sum_k a_k x_k)        params a[d], u_1
  *      PG_CORNER_PEAK   (1 + sum_k a_k x_k)^-(d+1)          params a[d]
  *      PG_MONOMIAL      prod_k x_k^alpha_k                  params alpha[d]
- *    (Section 4.1's test functions belong to these families.)
+ *      PG_C0            exp(-sum_k a_k |x_k - u_k|)         params a[d], u[d]
+ *      PG_DISCONTINUOUS exp(sum_k a_k x_k) if every x_k < c_k, else 0
+ *                                                          params a[d], c[d]
+ *      PG_BOX           (sum_k x_k^2)^p                     params p (p >= 0)
+ *    (Section 4.1's test functions f1..f8 belong to these families.)
  *  - Dimensions PG_DIM_MIN..PG_DIM_MAX are supported.
  *  - One context serves one caller at a time; calls on one context must not
  *    overlap.
@@ -60,7 +64,10 @@ typedef enum {
     PG_GAUSSIAN = 1,
     PG_OSCILLATORY = 2,
     PG_CORNER_PEAK = 3,
-    PG_MONOMIAL = 4
+    PG_MONOMIAL = 4,
+    PG_C0 = 5,
+    PG_DISCONTINUOUS = 6,
+    PG_BOX = 7
 } pg_family;
 
 typedef struct pg_context pg_context;

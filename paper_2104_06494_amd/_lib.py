@@ -15,7 +15,8 @@ LIB_PATH = os.path.join(_HERE, "libpagani.so")
 
 PG_DIM_MIN, PG_DIM_MAX = 2, 10
 FAMILY_ID = {"product_peak": 0, "gaussian": 1, "oscillatory": 2,
-             "corner_peak": 3, "monomial": 4}
+             "corner_peak": 3, "monomial": 4, "c0": 5, "discontinuous": 6,
+             "box": 7}
 STATUS = {0: "OK", 1: "MAX_ITERS", 2: "MEMORY_EXHAUSTED", 3: "NO_ACTIVE",
           -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EUNSUPPORTED"}
 

@@ -192,6 +192,8 @@ int make_params(pg_context *ctx, const pg_integrand *f, FParams *P) {
     case PG_PRODUCT_PEAK: case PG_GAUSSIAN: need = 2 * d; break;
     case PG_OSCILLATORY: need = d + 1; break;
     case PG_CORNER_PEAK: case PG_MONOMIAL: need = d; break;
+    case PG_C0: case PG_DISCONTINUOUS: need = 2 * d; break;
+    case PG_BOX: need = 1; break;
     default: return fail(ctx, PG_EUNSUPPORTED, "unknown family %d", f->family);
     }
     if (f->n_params != need)
@@ -223,6 +225,24 @@ int make_params(pg_context *ctx, const pg_integrand *f, FParams *P) {
         for (int k = 0; k < d; ++k) P->p[k] = p[k];
         P->p[d] = 2.0 * M_PI * p[d];
         break;
+    case PG_C0: case PG_DISCONTINUOUS:
+        for (int k = 0; k < 2 * d; ++k) P->p[k] = p[k];
+        break;
+    case PG_BOX: {
+        const double q = p[0];
+        if (q < 0) return fail(ctx, PG_EINVAL, "box power p = %g < 0", q);
+        P->p[0] = q;
+        if (q <= 64 && q == std::floor(q)) {
+            P->p[1] = 0.0;
+            P->p[2] = q;
+        } else if (q <= 64 && 2 * q == std::floor(2 * q)) {
+            P->p[1] = 1.0;
+            P->p[2] = std::floor(q);
+        } else {
+            P->p[1] = 2.0;
+        }
+        break;
+    }
     default:
         for (int k = 0; k < d; ++k) P->p[k] = p[k];
         if (f->family == PG_MONOMIAL)

@@ -21,6 +21,8 @@ constexpr int TRIAL_THREADS = 1024;
 // search's possible next steps.
 constexpr int TRIAL_DEPTH = 4;
 constexpr int TRIAL_M = (1 << TRIAL_DEPTH) - 1;
+// Waves (at most) sharing the 64 regions of an EVALUATE block.
+constexpr int EVAL_MAX_WAVES = 8;
 // Threads of the single-block reduce/scan kernels.
 constexpr int SCAN_THREADS = 1024;
 
@@ -30,6 +32,10 @@ constexpr int SCAN_THREADS = 1024;
 //  oscillatory:  p[k] = a_k,    p[d]   = 2 pi u_1
 //  corner peak:  p[k] = a_k
 //  monomial:     p[k] = alpha_k
+//  c0:           p[k] = a_k,    p[d+k] = u_k
+//  discontinuous: p[k] = a_k,   p[d+k] = c_k
+//  box:          p[0] = p, p[1] = 0 (integer p, p[2] = p), 1 (p = p[2] +
+//                1/2), 2 (other p: pow)
 struct FParams {
     double p[2 * PG_DIM_MAX + 2];
 };
