@@ -246,6 +246,47 @@ def adjoint_mode(args):
     print(json.dumps({"mode": "adjoint", **adjoint(args)}), flush=True)
 
 
+def suite_mode(args):
+    """The paper's test suite (Section 4.1, f1..f8) over its tolerance sweep
+    (1e-3 down to 1.024e-10, a fifth at a time), each integrand until its
+    first run that does not converge, as the paper reports it; then the
+    filtering ablation (threshold search off) on the same sweep for the
+    5-d f4. One JSON line per run. Context of 2^26 regions (20 GB at d=8)."""
+    import torch
+    import paper_2104_06494_amd as pg
+    import workloads as W
+    from workloads import closed_forms as cf
+
+    torch.cuda.set_device(0)
+    ctx = pg.Context(capacity=args.suite_capacity, dim_max=8)
+    tols = W.paper_tolerances()
+    runs = [(name, wl, 1) for name, wl in W.paper_suite()]
+    runs += [(name + "_no_threshold", wl, 0) for name, wl in W.paper_suite()
+             if name == "f4_d5"]
+    for name, wl, thr in runs:
+        if args.suite_only and not name.startswith(args.suite_only):
+            continue
+        ex = cf.exact(wl.family, wl.params, wl.d)
+        ctx.integrate_workload(wl, rel_tol=tols[0], max_regions=0, threshold_filter=thr)
+        for tol in tols:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = ctx.integrate_workload(wl, rel_tol=tol, max_regions=0, threshold_filter=thr)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0)
+            print(json.dumps({"mode": "suite", "integrand": name, "rel_tol": tol,
+                              "status": r.status_name, "estimate": r.estimate,
+                              "true_rel_err": abs(r.estimate - ex) / abs(ex),
+                              "est_rel_err": r.error / abs(r.estimate),
+                              "ms": ms, "iterations": r.iterations,
+                              "regions_evaluated": r.regions_evaluated,
+                              "peak_regions": r.peak_regions, "evals_per_s":
+                              r.fevals / (ms * 1e-3)}), flush=True)
+            if r.status_name != "OK":
+                break
+    ctx.close()
+
+
 def batched_mode(args):
     """The batched comparison alone (for profiling)."""
     print(json.dumps({"mode": "batched", **batched(args)}), flush=True)
@@ -301,8 +342,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", choices=["headline", "batched", "adjoint", "integrand",
-                                       "copy"],
+    ap.add_argument("--mode", choices=["headline", "batched", "adjoint", "suite",
+                                       "integrand", "copy"],
                     default="headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
@@ -313,6 +354,10 @@ def main():
                     help="batched run without the single-run comparison")
     ap.add_argument("--batch-count", type=int, default=0,
                     help="first integrals of the batch only (0 = all 1024)")
+    ap.add_argument("--suite-capacity", type=int, default=1 << 26,
+                    help="regions of the context the suite sweep runs in")
+    ap.add_argument("--suite-only", default="",
+                    help="suite integrands whose name starts with this only")
     ap.add_argument("--batch-slots", type=int, default=64,
                     help="integrals in flight in the batched run (each "
                          "reserves 2^21 regions of workspace)")
@@ -323,7 +368,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     {"headline": headline, "batched": batched_mode, "adjoint": adjoint_mode,
-     "integrand": integrand_mode,
+     "suite": suite_mode, "integrand": integrand_mode,
      "copy": copy_mode}[args.mode](args)
 
 
