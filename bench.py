@@ -38,7 +38,7 @@ F_GAUSSIAN_D5 = 47.0
 # HBM bytes per evaluate launch of this workload from FETCH_SIZE / WRITE_SIZE
 # (scaled by a plain copy), valid only for the kernel source they were taken
 # on (first 16 hex digits of its sha256); reported as null otherwise.
-EVAL_TRAFFIC = {"bytes_per_launch": 37796101.0, "kernel_sha256": "d059381e737079ed",
+EVAL_TRAFFIC = {"bytes_per_launch": 37796192.0, "kernel_sha256": "7274ebe465c30795",
                 "profile": "profiles/evaluate_gaussian_d5_counters.txt"}
 # MI355X FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz.
 PEAK_FP64_TFLOPS = 78.6
@@ -46,7 +46,7 @@ PEAK_FP64_TFLOPS = 78.6
 
 def _kernel_sha():
     import hashlib
-    path = os.path.join(ROOT, "paper_2104_06494_amd", "csrc", "pg_evaluate.hip")
+    path = os.path.join(ROOT, "paper_2104_06494_amd", "csrc", "pg_eval_kernels.hpp")
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
