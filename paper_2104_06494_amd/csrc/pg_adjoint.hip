@@ -108,7 +108,8 @@ __device__ __forceinline__ void point_grad(const double (&x)[D],
     }
 }
 
-// Derivative of one region's rule value without the volume factor, over
+// Derivative of one region's rule value (orbit weights times the volume,
+// wv, added into g), over
 // the points of the degree-7 rule: the centre; the axis units (+-lambda2,
 // +-lambda3 on one axis) and pair units (the four sign choices of lambda4
 // on two axes), unrolled with the moving axes as compile-time indices so a
@@ -119,8 +120,8 @@ template <int FAM, int D>
 __device__ __forceinline__ void region_grad(const double (&c)[D],
                                             const double (&h)[D],
                                             const GParams &P, const Rule &R,
-                                            double *g) {
-    point_grad<FAM, D>(c, P, R.w7[0], g);
+                                            const double (&wv)[5], double *g) {
+    point_grad<FAM, D>(c, P, wv[0], g);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
 #pragma unroll 1
@@ -130,7 +131,7 @@ __device__ __forceinline__ void region_grad(const double (&c)[D],
             for (int k = 0; k < D; ++k) x[k] = c[k];
             const double lam = q < 2 ? R.lam2 : R.lam3;
             x[i] = fma((q & 1) ? -1.0 : 1.0, lam * h[i], c[i]);
-            point_grad<FAM, D>(x, P, q < 2 ? R.w7[1] : R.w7[2], g);
+            point_grad<FAM, D>(x, P, q < 2 ? wv[1] : wv[2], g);
         }
     }
 #pragma unroll
@@ -144,7 +145,7 @@ __device__ __forceinline__ void region_grad(const double (&c)[D],
                 for (int k = 0; k < D; ++k) x[k] = c[k];
                 x[i] = fma((q & 2) ? -1.0 : 1.0, R.lam4 * h[i], c[i]);
                 x[j] = fma((q & 1) ? -1.0 : 1.0, R.lam4 * h[j], c[j]);
-                point_grad<FAM, D>(x, P, R.w7[3], g);
+                point_grad<FAM, D>(x, P, wv[3], g);
             }
         }
     }
@@ -156,7 +157,7 @@ __device__ __forceinline__ void region_grad(const double (&c)[D],
 #pragma unroll
             for (int k = 0; k < D; ++k)
                 x[k] = fma(((b >> k) & 1) ? -1.0 : 1.0, R.lam5 * h[k], c[k]);
-            point_grad<FAM, D>(x, P, R.w7[4], g);
+            point_grad<FAM, D>(x, P, wv[4], g);
         }
     }
 }
@@ -237,12 +238,10 @@ k_batch_adjoint(const BSeg *__restrict__ segs, const BInst *__restrict__ inst,
             }
         }
         if (out.owner) out.owner[out.base + leaf0 + j] = I.owner;
-        double g[NP];
+        double wv[5];
 #pragma unroll
-        for (int q = 0; q < NP; ++q) g[q] = 0.0;
-        region_grad<FAM, D>(c, h, P, R, g);
-#pragma unroll
-        for (int q = 0; q < NP; ++q) G[q] = fma(vol, g[q], G[q]);
+        for (int o = 0; o < 5; ++o) wv[o] = vol * R.w7[o];
+        region_grad<FAM, D>(c, h, P, R, wv, G);
     }
     // fixed-order block sum: butterfly within waves, then waves in order
 #pragma unroll
