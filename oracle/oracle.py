@@ -56,8 +56,11 @@ def lib():
     L.oracle_rule.argtypes = [C.c_int, _dp, _dp, _dp]
     L.oracle_eval_regions.restype = C.c_int
     L.oracle_eval_regions.argtypes = [C.c_int, C.c_int, _dp, C.c_long, _dp, _dp,
-                                      C.c_long, _dp, _dp, _u8, C.c_void_p,
-                                      C.c_void_p, C.c_void_p, C.c_void_p]
+                                      C.c_long, C.c_int, _dp, _dp, _u8,
+                                      C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_void_p]
+    L.oracle_null_rules.restype = None
+    L.oracle_null_rules.argtypes = [C.c_int, _dp]
     L.oracle_two_level.restype = None
     L.oracle_two_level.argtypes = [C.c_long, _dp, _dp, _dp]
     L.oracle_classify.restype = None
@@ -78,7 +81,7 @@ def lib():
     L.oracle_integrate.restype = C.c_int
     L.oracle_integrate.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, C.c_double,
                                    C.c_double, C.c_int, C.c_int, C.c_int,
-                                   C.c_int, C.c_int64, C.c_char_p, _dp,
+                                   C.c_int, C.c_int, C.c_int64, C.c_char_p, _dp,
                                    np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS"),
                                    C.POINTER(ReplayStats), C.c_void_p, C.c_void_p,
                                    C.c_void_p]
@@ -111,6 +114,17 @@ def rule(d: int):
     return w7, w5, lam
 
 
+ERROR_RULE = {"raw": 0, "null4": 1}
+
+
+def null_rules(d: int) -> np.ndarray:
+    """[4, 5] per-orbit weights of the four null rules of reading R9
+    (degrees 5, 3, 3, 1), each with the degree-7 rule's norm."""
+    out = np.zeros(20)
+    lib().oracle_null_rules(d, out)
+    return out.reshape(4, 5)
+
+
 def f(family: str, params, x) -> float:
     """One integrand value."""
     x = _f64(x)
@@ -128,9 +142,10 @@ class RegionEval:
     floorD: np.ndarray
 
 
-def eval_regions(family: str, d: int, params, lo, w) -> RegionEval:
-    """Evaluate step (Section 3.2): V, raw E, split axis K for each box.
-    ``lo`` and ``w`` are [d, n] (structure of arrays)."""
+def eval_regions(family: str, d: int, params, lo, w, error_rule="raw") -> RegionEval:
+    """Evaluate step (Section 3.2): V, E (|R7 - R5|, or the four-null-rule
+    estimate of reading R9 with error_rule="null4"), split axis K for each
+    box. ``lo`` and ``w`` are [d, n] (structure of arrays)."""
     lo, w = _f64(lo), _f64(w)
     n = lo.shape[1]
     V, E = np.zeros(n), np.zeros(n)
@@ -138,8 +153,8 @@ def eval_regions(family: str, d: int, params, lo, w) -> RegionEval:
     D = np.zeros((n, d))
     fv, fe, fd = np.zeros(n), np.zeros(n), np.zeros(n)
     rc = lib().oracle_eval_regions(FAMILY_ID[family], d, _f64(params), n, lo, w,
-                                   n, V, E, K, _ptr(D), _ptr(fv), _ptr(fe),
-                                   _ptr(fd))
+                                   n, ERROR_RULE[error_rule], V, E, K, _ptr(D),
+                                   _ptr(fv), _ptr(fe), _ptr(fd))
     if rc:
         raise ValueError(f"oracle_eval_regions: {rc}")
     return RegionEval(V, E, K, D, fv, fe, fd)
@@ -231,7 +246,8 @@ class OracleResult:
 def integrate(family: str, d: int, params, lo=None, hi=None, rel_tol=1e-3,
               abs_tol=1e-20, init_splits=4, max_iters=100, relerr_filter=1,
               threshold_filter=1, max_regions=1 << 22,
-              replay_path: str | None = None, grad: bool = False) -> OracleResult:
+              replay_path: str | None = None, grad: bool = False,
+              error_rule: str = "raw") -> OracleResult:
     """PAGANI main loop (Algorithm 2), free mode or replaying a GPU trace.
     With grad=True also the derivative of the estimate with respect to the
     parameters over the partition the run ends on (its leaves: every region
@@ -247,7 +263,8 @@ def integrate(family: str, d: int, params, lo=None, hi=None, rel_tol=1e-3,
     lv = np.zeros(1)
     rc = lib().oracle_integrate(FAMILY_ID[family], d, _f64(params), lo, hi,
                                 rel_tol, abs_tol, init_splits, max_iters,
-                                relerr_filter, threshold_filter, max_regions,
+                                relerr_filter, threshold_filter,
+                                ERROR_RULE[error_rule], max_regions,
                                 replay_path.encode() if replay_path else None,
                                 out_d, out_i, C.byref(rs), _ptr(g), _ptr(ga), _ptr(lv))
     if rc:
@@ -298,5 +315,5 @@ def integrate_workload(wl, **kw) -> OracleResult:
 __all__ = ["lib", "npoints", "rule", "f", "eval_regions", "two_level",
            "classify", "csum", "threshold_search", "filter_split",
            "uniform_split", "integrate", "integrate_workload", "OracleResult",
-           "grad_f", "grad_regions",
+           "grad_f", "grad_regions", "null_rules", "ERROR_RULE",
            "RegionEval", "FAMILY_ID", "STATUS"]

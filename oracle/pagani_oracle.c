@@ -32,7 +32,11 @@
  *       error finished regions may still carry, P_max relaxed only under
  *       memory pressure, 10 direction changes / 64 trials at most;
  *   R7  filter/split order: stable compaction; children of the j-th active
- *       region go to j (lower half) and j + n_active (upper half).
+ *       region go to j (lower half) and j + n_active (upper half);
+ *   R9  optional error estimate from four null rules (Section 3.2 compares
+ *       the basic rule with four further rules; Section 2 on Cuhre): the
+ *       fully symmetric null rules of degrees 5, 3, 3, 1 of the same
+ *       points, and a decay test between their magnitudes (below).
  */
 #include <math.h>
 #include <stdint.h>
@@ -149,6 +153,114 @@ void oracle_rule(int d, double w7[5], double w5[5], double lambda[5])
     lambda[4] = sqrt(9.0 / 19.0);
 }
 
+/* ------------------------------------------------------------------------
+ * Null rules (reading R9). A fully symmetric rule is one weight per orbit,
+ * u[o]. Over the points of [-1,1]^d it sums to zero on x^alpha iff
+ * <u, g_alpha> = 0, where <u, v> = sum_o m_o u_o v_o (m_o points in orbit
+ * o: the dot product of the per-point weights) and g_alpha[o] is the mean
+ * of x^alpha over orbit o. Odd monomials vanish by symmetry, and up to
+ * degree 5 the even ones reduce to 1, x1^2, x1^4 and x1^2 x2^2. The
+ * Gram-Schmidt basis q0..q4 of g_1, g_x2, g_x4, g_x2y2 (and one more
+ * vector) splits the rules by degree: rules that vanish on every
+ * polynomial of degree <= 5 are span{q4}, of degree <= 3 span{q2, q3, q4},
+ * of degree <= 1 span{q1, ..., q4}. So
+ *   nul[0] = q4   (degree 5: the direction of R7 - R5),
+ *   nul[1] = q2, nul[2] = q3   (degree 3, orthogonal to nul[0]),
+ *   nul[3] = q1   (degree 1, orthogonal to the others),
+ * each scaled to the norm of the degree-7 rule's per-point weights.
+ * ---------------------------------------------------------------------- */
+static double or_ip(const double m[5], const double *u, const double *v)
+{
+    double s = 0.0;
+    int o;
+    for (o = 0; o < 5; o++) s = s + m[o] * u[o] * v[o];
+    return s;
+}
+
+void oracle_null_rules(int d, double nul[4][5])
+{
+    double w7[5], w5[5], lam[5], m[5], L2[5], L4[5], g[6][5], q[5][5];
+    double n7;
+    int o, i, j, nq = 0;
+    oracle_rule(d, w7, w5, lam);
+    m[0] = 1.0;
+    m[1] = 2.0 * d;
+    m[2] = 2.0 * d;
+    m[3] = 2.0 * d * (d - 1);
+    m[4] = ldexp(1.0, d);
+    for (o = 0; o < 5; o++) {
+        L2[o] = lam[o] * lam[o];
+        L4[o] = L2[o] * L2[o];
+    }
+    /* orbit means: axis orbits put lambda on x1 at 2 of 2d points; pairs
+       involve axis 1 at 4(d-1) of 2d(d-1) points and axes 1, 2 together at
+       4 of them; every vertex has |x_k| = lambda5 */
+    for (o = 0; o < 5; o++) g[0][o] = 1.0;
+    g[1][0] = 0.0; g[1][1] = L2[1] / d; g[1][2] = L2[2] / d;
+    g[1][3] = 2.0 * L2[3] / d; g[1][4] = L2[4];
+    g[2][0] = 0.0; g[2][1] = L4[1] / d; g[2][2] = L4[2] / d;
+    g[2][3] = 2.0 * L4[3] / d; g[2][4] = L4[4];
+    g[3][0] = 0.0; g[3][1] = 0.0; g[3][2] = 0.0;
+    g[3][3] = d > 1 ? 2.0 * L4[3] / (d * (d - 1.0)) : 0.0; g[3][4] = L4[4];
+    /* completions: the centre alone, then a vertex-only rule */
+    for (o = 0; o < 5; o++) {
+        g[4][o] = o == 0 ? 1.0 : 0.0;
+        g[5][o] = o == 4 ? 1.0 : 0.0;
+    }
+    for (i = 0; i < 6 && nq < 5; i++) {
+        double v[5], nv, n0 = sqrt(or_ip(m, g[i], g[i]));
+        for (o = 0; o < 5; o++) v[o] = g[i][o];
+        for (j = 0; j < nq; j++) {
+            double c = or_ip(m, v, q[j]);
+            for (o = 0; o < 5; o++) v[o] = v[o] - c * q[j][o];
+        }
+        nv = sqrt(or_ip(m, v, v));
+        if (!(nv > 1e-9 * n0)) continue;      /* dependent: skip */
+        for (o = 0; o < 5; o++) q[nq][o] = v[o] / nv;
+        nq++;
+    }
+    n7 = sqrt(or_ip(m, w7, w7));
+    for (o = 0; o < 5; o++) {
+        nul[0][o] = n7 * q[4][o];
+        nul[1][o] = n7 * q[2][o];
+        nul[2][o] = n7 * q[3][o];
+        nul[3][o] = n7 * q[1][o];
+    }
+}
+
+/* The R9 estimate from the magnitudes of the null-rule values,
+ *   e5 = |N1|,  e3 = sqrt((N2^2 + N3^2) / 2),  e1 = |N4|:
+ * for a smooth f they fall by a factor r ~ (h f-scale)^2 per two degrees
+ * (e1 ~ h^2, e3 ~ h^4, e5 ~ h^6) while the degree-7 rule errs by ~h^8,
+ * about r^2 e3 by the same decay. With r = max(e3 / e1, e5 / e3) at most
+ * OR_NULL_RC (each degree step shrinks by at least two) the error is
+ * extrapolated as kappa_d r^2 e3; otherwise the values do not decay like a
+ * resolved integrand's and the estimate is the largest of them.
+ * kappa_d = 2 max(1, L_d) rounded up to two digits, L_d the supremum over
+ * directions a of the limit (|a| -> 0) of the true error over r^2 e3 for
+ * f = exp(a.x) (reached with one large and d-1 equal components; the
+ * tests recompute it): L_d = 0.050, 0.354, 1.896, 7.037, 8.724, 10.17,
+ * 12.03, 14.28, 16.86 for d = 2..10. */
+static const double OR_NULL_KAPPA[11] = {0.0, 0.0, 2.0, 2.0, 3.8, 15.0,
+                                         18.0, 21.0, 25.0, 29.0, 34.0};
+#define OR_NULL_RC 0.5
+#define OR_NULL_DMAX 10
+
+static double or_ratio(double a, double b)
+{
+    if (a == 0.0) return 0.0;
+    return b == 0.0 ? INFINITY : a / b;
+}
+
+static double or_null4_error(double kappa, double e5, double e3, double e1)
+{
+    double r = or_ratio(e3, e1), r2 = or_ratio(e5, e3), big;
+    if (r2 > r) r = r2;
+    if (r <= OR_NULL_RC) return kappa * r * r * e3;
+    big = e5 > e3 ? e5 : e3;
+    return big > e1 ? big : e1;
+}
+
 /* Fourth-difference tie band of reading R3: relative band and the noise
    allowance relative to the magnitude of the values entering a difference. */
 #define OR_AXIS_TIE 1e-10
@@ -170,7 +282,7 @@ void oracle_rule(int d, double w7[5], double w5[5], double lambda[5])
 static void eval_region(int family, int d, const double *par,
                         const double *lo, const double *w,
                         const double w7[5], const double w5[5],
-                        const double lam[5],
+                        const double lam[5], const double (*nul)[5],
                         double *V, double *E, int *K, double *Dout,
                         double *floorV, double *floorE, double *floorD)
 {
@@ -247,6 +359,42 @@ static void eval_region(int family, int d, const double *par,
     *E = fabs(vol * sumN);
     *floorV = OR_FLOOR_ULPS * 2.220446049250313e-16 * vol * fl7;
     *floorE = OR_FLOOR_ULPS * 2.220446049250313e-16 * vol * flN;
+    if (nul) {
+        /* reading R9; its floor: the spread of the estimate over the
+           corners of the rounding box of (e5, e3, e1), which also covers a
+           decay test that rounding could flip */
+        double nv[4], fl[4], e5, e3, e1, f5, f3, f1, lo_e, hi_e;
+        int c;
+        for (i = 0; i < 4; i++) {
+            nv[i] = 0.0;
+            fl[i] = 0.0;
+            for (k = 0; k < 5; k++) {
+                nv[i] = nv[i] + nul[i][k] * S[k];
+                fl[i] = fl[i] + fabs(nul[i][k]) * A[k];
+            }
+            nv[i] = vol * nv[i];
+            fl[i] = OR_FLOOR_ULPS * 2.220446049250313e-16 * vol * fl[i];
+        }
+        e5 = fabs(nv[0]);
+        e3 = sqrt((nv[1] * nv[1] + nv[2] * nv[2]) / 2.0);
+        e1 = fabs(nv[3]);
+        f5 = fl[0];
+        f3 = fl[1] > fl[2] ? fl[1] : fl[2];
+        f1 = fl[3];
+        *E = or_null4_error(OR_NULL_KAPPA[d], e5, e3, e1);
+        lo_e = *E;
+        hi_e = *E;
+        for (c = 0; c < 8; c++) {
+            double a5 = e5 + ((c & 1) ? f5 : -f5);
+            double a3 = e3 + ((c & 2) ? f3 : -f3);
+            double a1 = e1 + ((c & 4) ? f1 : -f1);
+            double ec = or_null4_error(OR_NULL_KAPPA[d], a5 > 0 ? a5 : 0.0,
+                                       a3 > 0 ? a3 : 0.0, a1 > 0 ? a1 : 0.0);
+            if (ec < lo_e) lo_e = ec;
+            if (ec > hi_e) hi_e = ec;
+        }
+        *floorE = hi_e - *E > *E - lo_e ? hi_e - *E : *E - lo_e;
+    }
 
     /* split axis: fourth divided difference, lambda2^2 / lambda3^2 = 1/7 */
     dmax = 0.0;
@@ -281,21 +429,27 @@ static void eval_region(int family, int d, const double *par,
  */
 int oracle_eval_regions(int family, int d, const double *par, long n,
                         const double *lo, const double *w, long ld,
-                        double *V, double *E, uint8_t *K, double *Dout,
-                        double *floorV, double *floorE, double *floorD)
+                        int err_rule, double *V, double *E, uint8_t *K,
+                        double *Dout, double *floorV, double *floorE,
+                        double *floorD)
 {
     double w7[5], w5[5], lam[5], l[OR_DMAX], ww[OR_DMAX], fv, fe, fd;
+    double nul[4][5];
     long i;
     int k, kk;
     if (d < 1 || d > OR_DMAX || n < 0) return OR_EINVAL;
+    if (err_rule != 0 && (err_rule != 1 || d < 2 || d > OR_NULL_DMAX))
+        return OR_EINVAL;
     oracle_rule(d, w7, w5, lam);
+    if (err_rule) oracle_null_rules(d, nul);
     for (i = 0; i < n; i++) {
         for (k = 0; k < d; k++) {
             l[k] = lo[k * ld + i];
             ww[k] = w[k * ld + i];
         }
-        eval_region(family, d, par, l, ww, w7, w5, lam, &V[i], &E[i], &kk,
-                    Dout ? Dout + i * d : NULL, &fv, &fe, &fd);
+        eval_region(family, d, par, l, ww, w7, w5, lam,
+                    err_rule ? (const double (*)[5])nul : NULL, &V[i], &E[i],
+                    &kk, Dout ? Dout + i * d : NULL, &fv, &fe, &fd);
         K[i] = (uint8_t)kk;
         if (floorV) floorV[i] = fv;
         if (floorE) floorE[i] = fe;
@@ -736,7 +890,7 @@ static double now_s(void)
 int oracle_integrate(int family, int d, const double *par,
                      const double *a, const double *b,
                      double tau_rel, double tau_abs, int g, int it_max,
-                     int relerr_filter, int threshold_filter,
+                     int relerr_filter, int threshold_filter, int err_rule,
                      int64_t max_regions, const char *replay_path,
                      double *out_d, int64_t *out_i, or_replay_stats *rs,
                      double *grad, double *grad_abs, double *leaf_v)
@@ -760,6 +914,8 @@ int oracle_integrate(int family, int d, const double *par,
     int np = 0;
 
     if (d < 1 || d > OR_DMAX || g < 1 || it_max < 1) return OR_EINVAL;
+    if (err_rule != 0 && (err_rule != 1 || d < 2 || d > OR_NULL_DMAX))
+        return OR_EINVAL;
     if (!(tau_rel > 0.0) && !(tau_abs > 0.0)) return OR_EINVAL;
     for (k = 0; k < d; k++) if (!(a[k] < b[k])) return OR_EINVAL;
     s = 1;
@@ -838,7 +994,8 @@ int oracle_integrate(int family, int d, const double *par,
 
         /* Evaluate: V, E, K for every region of H */
         t1 = now_s();
-        oracle_eval_regions(family, d, par, s, lo, w, s, V, E, K, Dd, fV, fE, fD);
+        oracle_eval_regions(family, d, par, s, lo, w, s, err_rule, V, E, K,
+                            Dd, fV, fE, fD);
         t_eval += now_s() - t1;
         n_eval += s;
 

@@ -72,14 +72,30 @@ SUITE_MUTANTS = {
                         "            s = s + x[i];\n        return pow(s, p[0]);"),
 }
 
+# mistakes in the four null rules and the estimate built on them
+NULL4_MUTANTS = {
+    "null_pair_multiplicity": ("m[3] = 2.0 * d * (d - 1);", "m[3] = 1.0 * d * (d - 1);"),
+    "null_pair_mean": ("g[1][3] = 2.0 * L2[3] / d;", "g[1][3] = L2[3] / d;"),
+    "null_degree_swap": ("nul[1][o] = n7 * q[2][o];", "nul[1][o] = n7 * q[1][o];"),
+    "null_rms_half": ("e3 = sqrt((nv[1] * nv[1] + nv[2] * nv[2]) / 2.0);",
+                      "e3 = sqrt(nv[1] * nv[1] + nv[2] * nv[2]);"),
+    "null_r_power": ("return kappa * r * r * e3;", "return kappa * r * e3;"),
+    "null_ratio_inverted": ("double r = or_ratio(e3, e1), r2 = or_ratio(e5, e3), big;",
+                            "double r = or_ratio(e1, e3), r2 = or_ratio(e5, e3), big;"),
+    "null_kappa_d5": ("{0.0, 0.0, 2.0, 2.0, 3.8, 15.0,", "{0.0, 0.0, 2.0, 2.0, 3.8, 7.0,"),
+    "null_branch_inverted": ("if (r <= OR_NULL_RC) return", "if (r > OR_NULL_RC) return"),
+    "null_smallest_magnitude": ("return big > e1 ? big : e1;", "return big < e1 ? big : e1;"),
+}
+
 CASES = [(n, "test_oracle_pins.py") for n in sorted(MUTANTS)] + \
         [(n, "test_oracle_grad_pins.py") for n in sorted(GRAD_MUTANTS)] + \
-        [(n, "test_oracle_suite_pins.py") for n in sorted(SUITE_MUTANTS)]
+        [(n, "test_oracle_suite_pins.py") for n in sorted(SUITE_MUTANTS)] + \
+        [(n, "test_oracle_null4_pins.py") for n in sorted(NULL4_MUTANTS)]
 
 
 @pytest.mark.parametrize("name,pins", CASES, ids=[c[0] for c in CASES])
 def test_mutant_is_caught(name, pins, tmp_path):
-    old, new = {**MUTANTS, **GRAD_MUTANTS, **SUITE_MUTANTS}[name]
+    old, new = {**MUTANTS, **GRAD_MUTANTS, **SUITE_MUTANTS, **NULL4_MUTANTS}[name]
     src = open(SRC).read()
     assert src.count(old) == 1, f"mutation anchor not unique: {name}"
     mut = tmp_path / "mutant.c"
