@@ -70,6 +70,28 @@ typedef enum {
     PG_BOX = 7
 } pg_family;
 
+/*
+ * Error estimate of a region (the E of EVALUATE, Section 3.2):
+ *  PG_ERR_RAW    |R7 - R5|: the degree-7 rule against its embedded
+ *                degree-5 rule (the default).
+ *  PG_ERR_NULL4  four null rules of the same points (Section 3.2 compares
+ *                the basic rule with four further rules, as Cuhre does,
+ *                Section 2): N1 of degree 5, N2 and N3 of degree 3, N4 of
+ *                degree 1, fully symmetric, mutually orthogonal and of the
+ *                degree-7 rule's norm. With e5 = |N1|, e3 = rms(N2, N3),
+ *                e1 = |N4| and r = max(e3 / e1, e5 / e3): E = kappa_d r^2
+ *                e3 if r <= 1/2 (the values fall like a resolved smooth
+ *                integrand's), else max(e5, e3, e1); kappa_d = 2, 2, 3.8,
+ *                15, 18, 21, 25, 29, 34 for d = 2..10 (twice the worst
+ *                limit ratio of the true error to r^2 e3 over exp(a.x),
+ *                and at least 2). No extra integrand evaluations; the
+ *                split axis is unchanged.
+ */
+typedef enum {
+    PG_ERR_RAW = 0,
+    PG_ERR_NULL4 = 1
+} pg_error_rule;
+
 typedef struct pg_context pg_context;
 
 typedef struct {
@@ -90,10 +112,12 @@ typedef struct {
     int64_t max_regions;      /* cap on the live list; 0: context capacity */
     int timing;               /* 1: time each phase with HIP events */
     const char *trace_path;   /* non-NULL: write the decision trace (below) */
+    int error_rule;           /* pg_error_rule */
 } pg_options;
 
 /* Default options: rel_tol 1e-3, abs_tol 1e-20, g = 4, it_max = 100, both
-   filters on, cap = capacity, no timing, no trace. */
+   filters on, cap = capacity, no timing, no trace, error rule
+   PG_ERR_RAW. */
 void pg_default_options(pg_options *opt);
 
 typedef struct {
@@ -248,6 +272,14 @@ int pg_last_regions(const pg_context *ctx, pg_regions_view *out);
 int pg_evaluate(pg_context *ctx, const pg_integrand *f, int64_t n,
                 const double *lo, const double *w, int64_t ld, double *V,
                 double *E, uint8_t *K);
+
+/*
+ * pg_evaluate with the error estimate chosen by error_rule (pg_error_rule;
+ * PG_EINVAL for other values). V and K are the same as pg_evaluate's.
+ */
+int pg_evaluate_rule(pg_context *ctx, const pg_integrand *f, int error_rule,
+                     int64_t n, const double *lo, const double *w, int64_t ld,
+                     double *V, double *E, uint8_t *K);
 
 /*
  * The integrand alone: y[i] = f(x_i) for n points x_i with coordinates

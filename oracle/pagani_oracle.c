@@ -169,62 +169,73 @@ void oracle_rule(int d, double w7[5], double w5[5], double lambda[5])
  *   nul[3] = q1   (degree 1, orthogonal to the others),
  * each scaled to the norm of the degree-7 rule's per-point weights.
  * ---------------------------------------------------------------------- */
-static double or_ip(const double m[5], const double *u, const double *v)
+static long double or_ip(const long double m[5], const long double *u,
+                         const long double *v)
 {
-    double s = 0.0;
+    long double s = 0.0L;
     int o;
     for (o = 0; o < 5; o++) s = s + m[o] * u[o] * v[o];
     return s;
 }
 
+/* Derived in extended precision (long double) with the generators'
+   squares as exact fractions and each projection applied twice, then
+   rounded once to double, so that every weight is correct to about an
+   ulp (one pass in double loses up to 1e5 ulps on the small vertex weight
+   of N1 at d = 10). */
 void oracle_null_rules(int d, double nul[4][5])
 {
-    double w7[5], w5[5], lam[5], m[5], L2[5], L4[5], g[6][5], q[5][5];
-    double n7;
-    int o, i, j, nq = 0;
+    double w7[5], w5[5], lam[5];
+    long double m[5], L2[5], L4[5], g[6][5], q[5][5], n7;
+    int o, i, j, pass, nq = 0;
     oracle_rule(d, w7, w5, lam);
-    m[0] = 1.0;
-    m[1] = 2.0 * d;
-    m[2] = 2.0 * d;
-    m[3] = 2.0 * d * (d - 1);
-    m[4] = ldexp(1.0, d);
-    for (o = 0; o < 5; o++) {
-        L2[o] = lam[o] * lam[o];
-        L4[o] = L2[o] * L2[o];
-    }
+    m[0] = 1.0L;
+    m[1] = 2.0L * d;
+    m[2] = 2.0L * d;
+    m[3] = 2.0L * d * (d - 1);
+    m[4] = ldexpl(1.0L, d);
+    L2[0] = 0.0L;
+    L2[1] = 9.0L / 70.0L;
+    L2[2] = 9.0L / 10.0L;
+    L2[3] = 9.0L / 10.0L;
+    L2[4] = 9.0L / 19.0L;
+    for (o = 0; o < 5; o++) L4[o] = L2[o] * L2[o];
     /* orbit means: axis orbits put lambda on x1 at 2 of 2d points; pairs
        involve axis 1 at 4(d-1) of 2d(d-1) points and axes 1, 2 together at
        4 of them; every vertex has |x_k| = lambda5 */
-    for (o = 0; o < 5; o++) g[0][o] = 1.0;
-    g[1][0] = 0.0; g[1][1] = L2[1] / d; g[1][2] = L2[2] / d;
-    g[1][3] = 2.0 * L2[3] / d; g[1][4] = L2[4];
-    g[2][0] = 0.0; g[2][1] = L4[1] / d; g[2][2] = L4[2] / d;
-    g[2][3] = 2.0 * L4[3] / d; g[2][4] = L4[4];
-    g[3][0] = 0.0; g[3][1] = 0.0; g[3][2] = 0.0;
-    g[3][3] = d > 1 ? 2.0 * L4[3] / (d * (d - 1.0)) : 0.0; g[3][4] = L4[4];
+    for (o = 0; o < 5; o++) g[0][o] = 1.0L;
+    g[1][0] = 0.0L; g[1][1] = L2[1] / d; g[1][2] = L2[2] / d;
+    g[1][3] = 2.0L * L2[3] / d; g[1][4] = L2[4];
+    g[2][0] = 0.0L; g[2][1] = L4[1] / d; g[2][2] = L4[2] / d;
+    g[2][3] = 2.0L * L4[3] / d; g[2][4] = L4[4];
+    g[3][0] = 0.0L; g[3][1] = 0.0L; g[3][2] = 0.0L;
+    g[3][3] = d > 1 ? 2.0L * L4[3] / (d * (d - 1.0L)) : 0.0L; g[3][4] = L4[4];
     /* completions: the centre alone, then a vertex-only rule */
     for (o = 0; o < 5; o++) {
-        g[4][o] = o == 0 ? 1.0 : 0.0;
-        g[5][o] = o == 4 ? 1.0 : 0.0;
+        g[4][o] = o == 0 ? 1.0L : 0.0L;
+        g[5][o] = o == 4 ? 1.0L : 0.0L;
     }
     for (i = 0; i < 6 && nq < 5; i++) {
-        double v[5], nv, n0 = sqrt(or_ip(m, g[i], g[i]));
+        long double v[5], nv, n0 = sqrtl(or_ip(m, g[i], g[i]));
         for (o = 0; o < 5; o++) v[o] = g[i][o];
-        for (j = 0; j < nq; j++) {
-            double c = or_ip(m, v, q[j]);
-            for (o = 0; o < 5; o++) v[o] = v[o] - c * q[j][o];
-        }
-        nv = sqrt(or_ip(m, v, v));
-        if (!(nv > 1e-9 * n0)) continue;      /* dependent: skip */
+        for (pass = 0; pass < 2; pass++)
+            for (j = 0; j < nq; j++) {
+                long double c = or_ip(m, v, q[j]);
+                for (o = 0; o < 5; o++) v[o] = v[o] - c * q[j][o];
+            }
+        nv = sqrtl(or_ip(m, v, v));
+        if (!(nv > 1e-9L * n0)) continue;     /* dependent: skip */
         for (o = 0; o < 5; o++) q[nq][o] = v[o] / nv;
         nq++;
     }
-    n7 = sqrt(or_ip(m, w7, w7));
+    n7 = 0.0L;
+    for (o = 0; o < 5; o++) n7 = n7 + m[o] * (long double)w7[o] * w7[o];
+    n7 = sqrtl(n7);
     for (o = 0; o < 5; o++) {
-        nul[0][o] = n7 * q[4][o];
-        nul[1][o] = n7 * q[2][o];
-        nul[2][o] = n7 * q[3][o];
-        nul[3][o] = n7 * q[1][o];
+        nul[0][o] = (double)(n7 * q[4][o]);
+        nul[1][o] = (double)(n7 * q[2][o]);
+        nul[2][o] = (double)(n7 * q[3][o]);
+        nul[3][o] = (double)(n7 * q[1][o]);
     }
 }
 
@@ -239,8 +250,8 @@ void oracle_null_rules(int d, double nul[4][5])
  * kappa_d = 2 max(1, L_d) rounded up to two digits, L_d the supremum over
  * directions a of the limit (|a| -> 0) of the true error over r^2 e3 for
  * f = exp(a.x) (reached with one large and d-1 equal components; the
- * tests recompute it): L_d = 0.050, 0.354, 1.896, 7.037, 8.724, 10.17,
- * 12.03, 14.28, 16.86 for d = 2..10. */
+ * tests recompute it): L_d = 0.050, 0.354, 1.896, 7.038, 8.724, 10.17,
+ * 12.03, 14.28, 16.87 for d = 2..10. */
 static const double OR_NULL_KAPPA[11] = {0.0, 0.0, 2.0, 2.0, 3.8, 15.0,
                                          18.0, 21.0, 25.0, 29.0, 34.0};
 #define OR_NULL_RC 0.5

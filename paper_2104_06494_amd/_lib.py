@@ -17,6 +17,7 @@ PG_DIM_MIN, PG_DIM_MAX = 2, 10
 FAMILY_ID = {"product_peak": 0, "gaussian": 1, "oscillatory": 2,
              "corner_peak": 3, "monomial": 4, "c0": 5, "discontinuous": 6,
              "box": 7}
+ERROR_RULE = {"raw": 0, "null4": 1}
 STATUS = {0: "OK", 1: "MAX_ITERS", 2: "MEMORY_EXHAUSTED", 3: "NO_ACTIVE",
           -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EUNSUPPORTED"}
 
@@ -24,7 +25,8 @@ EXPORTS = ["pg_default_options", "pg_workspace_bytes", "pg_context_create",
            "pg_context_destroy", "pg_context_set_stream", "pg_last_error",
            "pg_integrate", "pg_last_regions", "pg_evaluate", "pg_classify",
            "pg_threshold_search", "pg_filter_split", "pg_integrand_values",
-           "pg_integrate_batch", "pg_integrate_grad", "pg_integrate_batch_grad"]
+           "pg_integrate_batch", "pg_integrate_grad", "pg_integrate_batch_grad",
+           "pg_evaluate_rule"]
 
 
 class Integrand(C.Structure):
@@ -37,7 +39,7 @@ class Options(C.Structure):
                 ("init_splits", C.c_int), ("max_iters", C.c_int),
                 ("relerr_filter", C.c_int), ("threshold_filter", C.c_int),
                 ("max_regions", C.c_int64), ("timing", C.c_int),
-                ("trace_path", C.c_char_p)]
+                ("trace_path", C.c_char_p), ("error_rule", C.c_int)]
 
 
 class Result(C.Structure):
@@ -116,6 +118,9 @@ def load():
     L.pg_evaluate.argtypes = [vp, C.POINTER(Integrand), i64, vp, vp, i64, vp,
                               vp, vp]
     L.pg_evaluate.restype = C.c_int
+    L.pg_evaluate_rule.argtypes = [vp, C.POINTER(Integrand), C.c_int, i64, vp, vp,
+                                   i64, vp, vp, vp]
+    L.pg_evaluate_rule.restype = C.c_int
     L.pg_integrand_values.argtypes = [vp, C.POINTER(Integrand), i64, vp, i64, vp]
     L.pg_integrand_values.restype = C.c_int
     L.pg_classify.argtypes = [vp, i64, C.c_int, vp, vp, vp, C.c_double, C.c_int,

@@ -29,6 +29,14 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def _error_rule(rule):
+    if isinstance(rule, str):
+        if rule not in L.ERROR_RULE:
+            raise ValueError(f"error_rule must be one of {sorted(L.ERROR_RULE)}")
+        return L.ERROR_RULE[rule]
+    return int(rule)
+
+
 def _integrand(family, d, params):
     p = np.ascontiguousarray(params, dtype=np.float64)
     arr = (C.c_double * len(p))(*p.tolist())
@@ -134,8 +142,9 @@ class Context:
     def integrate(self, family, d, params, lo=None, hi=None, rel_tol=1e-3,
                   abs_tol=1e-20, init_splits=4, max_iters=100, relerr_filter=1,
                   threshold_filter=1, max_regions=0, timing=False,
-                  trace_path=None) -> IntegrateResult:
-        """Algorithm 2 over the box [lo, hi] (default unit cube)."""
+                  trace_path=None, error_rule="raw") -> IntegrateResult:
+        """Algorithm 2 over the box [lo, hi] (default unit cube). error_rule
+        "raw" (|R7 - R5|) or "null4" (the four-null-rule estimate)."""
         self._bind_stream()
         f, keep = _integrand(family, d, params)
         lo = np.zeros(d) if lo is None else np.asarray(lo, dtype=np.float64)
@@ -149,6 +158,7 @@ class Context:
         o.relerr_filter, o.threshold_filter = int(relerr_filter), int(threshold_filter)
         o.max_regions, o.timing = int(max_regions), int(bool(timing))
         o.trace_path = trace_path.encode() if trace_path else None
+        o.error_rule = _error_rule(error_rule)
         r = L.Result()
         with torch.cuda.device(self.device):
             rc = self.lib.pg_integrate(self.h, C.byref(f), clo, chi, C.byref(o),
@@ -159,29 +169,33 @@ class Context:
 
     def integrate_batch(self, family, d, params, rel_tol, abs_tol=None,
                         lo=None, hi=None, init_splits=4, max_iters=100,
-                        relerr_filter=1, threshold_filter=1, max_regions=0):
+                        relerr_filter=1, threshold_filter=1, max_regions=0,
+                        error_rule="raw"):
         """Algorithm 2 for B integrals of one family at once: params is
         [B, n_params], rel_tol a scalar or [B], abs_tol None (1e-20), a
         scalar or [B]; all share the box [lo, hi] and the options, and
         max_regions is the cap of each. Returns a list of B results."""
         return self._batch(family, d, params, rel_tol, abs_tol, lo, hi, init_splits,
-                           max_iters, relerr_filter, threshold_filter, max_regions)[0]
+                           max_iters, relerr_filter, threshold_filter, max_regions,
+                           error_rule=error_rule)[0]
 
     def integrate_batch_grad(self, family, d, params, rel_tol, abs_tol=None,
                              lo=None, hi=None, init_splits=4, max_iters=100,
                              relerr_filter=1, threshold_filter=1, max_regions=0,
-                             leaves_capacity=0):
+                             leaves_capacity=0, error_rule="raw"):
         """integrate_batch plus dI/dparams of every integral over its final
         partition: returns (results, grad [B, n_params] numpy, leaves). With
         leaves_capacity > 0, leaves is a dict of device tensors lo, w [d, n]
         and owner [n] (the partition's regions); otherwise None."""
         return self._batch(family, d, params, rel_tol, abs_tol, lo, hi, init_splits,
                            max_iters, relerr_filter, threshold_filter, max_regions,
-                           grad=True, leaves_capacity=leaves_capacity)
+                           grad=True, leaves_capacity=leaves_capacity,
+                           error_rule=error_rule)
 
     def integrate_grad(self, family, d, params, lo=None, hi=None, rel_tol=1e-3,
                        abs_tol=1e-20, init_splits=4, max_iters=100, relerr_filter=1,
-                       threshold_filter=1, max_regions=0, leaves_capacity=0):
+                       threshold_filter=1, max_regions=0, leaves_capacity=0,
+                       error_rule="raw"):
         """One integral and its parameter derivative through the C entry
         point pg_integrate_grad: returns (result, grad [n_params], leaves)."""
         self._bind_stream()
@@ -196,6 +210,7 @@ class Context:
         o.init_splits, o.max_iters = int(init_splits), int(max_iters)
         o.relerr_filter, o.threshold_filter = int(relerr_filter), int(threshold_filter)
         o.max_regions = int(max_regions)
+        o.error_rule = _error_rule(error_rule)
         g = np.zeros(f.n_params)
         lv, lt = self._leaves(d, leaves_capacity)
         r = L.Result()
@@ -227,7 +242,7 @@ class Context:
 
     def _batch(self, family, d, params, rel_tol, abs_tol, lo, hi, init_splits,
                max_iters, relerr_filter, threshold_filter, max_regions, grad=False,
-               leaves_capacity=0):
+               leaves_capacity=0, error_rule="raw"):
         self._bind_stream()
         P = np.ascontiguousarray(np.atleast_2d(np.asarray(params, dtype=np.float64)))
         B, npar = P.shape
@@ -248,6 +263,7 @@ class Context:
         o.init_splits, o.max_iters = int(init_splits), int(max_iters)
         o.relerr_filter, o.threshold_filter = int(relerr_filter), int(threshold_filter)
         o.max_regions = int(max_regions)
+        o.error_rule = _error_rule(error_rule)
         res = (L.Result * B)()
         fam = L.FAMILY_ID[family] if isinstance(family, str) else int(family)
         g = np.zeros((B, npar)) if grad else None
@@ -312,10 +328,10 @@ class Context:
                     K=view(v.K, n, torch.uint8), A=view(v.A, n, torch.uint8))
 
     # -- the steps of one iteration ---------------------------------------
-    def evaluate(self, family, params, lo, w):
+    def evaluate(self, family, params, lo, w, error_rule="raw"):
         """EVALUATE on the boxes [lo, lo + w] (lo, w: [d, n] float64 tensors,
         rows may be a strided view with unit element stride and a common row
-        stride). Returns (V, E, K)."""
+        stride). Returns (V, E, K); E by error_rule ("raw" or "null4")."""
         self._bind_stream()
         d, n = lo.shape
         ld = self._soa_ld(lo, w)
@@ -323,8 +339,8 @@ class Context:
         E = torch.empty_like(V)
         K = torch.empty(n, dtype=torch.uint8, device=self.device)
         f, keep = _integrand(family, d, params)
-        rc = self.lib.pg_evaluate(self.h, C.byref(f), n, _ptr(lo), _ptr(w), ld,
-                                  _ptr(V), _ptr(E), _ptr(K))
+        rc = self.lib.pg_evaluate_rule(self.h, C.byref(f), _error_rule(error_rule), n,
+                                       _ptr(lo), _ptr(w), ld, _ptr(V), _ptr(E), _ptr(K))
         if rc:
             raise self._err(rc)
         return V, E, K

@@ -158,7 +158,85 @@ int64_t npoints(int d) { return (int64_t(1) << d) + 2LL * d * d + 2LL * d + 1; }
 
 // Rule constants of the degree-7 rule and its degree-5 embedded rule per
 // orbit (weights relative to the box volume).
-Rule make_rule(int d) {
+// The four null rules of the point set (error rule PG_ERR_NULL4). A fully
+// symmetric rule u (one weight per orbit, m_o points each) vanishes on
+// x^alpha iff <u, g_alpha> = 0, with <u, v> = sum_o m_o u_o v_o and
+// g_alpha[o] the mean of x^alpha over orbit o; up to degree 5 only
+// alpha = 0, x1^2, x1^4, x1^2 x2^2 matter. Degree 5: the one direction
+// orthogonal to all four, which is w7 - w5. Degree 1: within span{g_0,
+// g_x2}, orthogonal to g_0. Degree 3 (orthogonal to the degree-5 one):
+// span{g_x4, g_x2y2} with span{g_0, g_x2} projected out, orthonormalised.
+// Each is scaled to the norm of w7. Worked in long double from the exact
+// rational weights and generator squares, then rounded once, so every
+// weight is correct to about an ulp (in double, one pass loses up to 1e5
+// ulps on the small vertex weights at d = 10).
+void make_null_rules(int d, const double w7d[5], double nul[4][5]) {
+    using LD = long double;
+    const LD m[5] = {1.0L, 2.0L * d, 2.0L * d, 2.0L * d * (d - 1),
+                     std::ldexp(1.0L, d)};
+    const LD s2[5] = {0.0L, 9.0L / 70.0L, 9.0L / 10.0L, 9.0L / 10.0L,
+                      9.0L / 19.0L};
+    const LD D9 = 19683.0L;
+    const LD w7[5] = {(12824.0L - 9120.0L * d + 400.0L * d * d) / D9,
+                      980.0L / 6561.0L, (1820.0L - 400.0L * d) / D9,
+                      200.0L / D9, 6859.0L / D9 / std::ldexp(1.0L, d)};
+    const LD w5[5] = {(729.0L - 950.0L * d + 50.0L * d * d) / 729.0L,
+                      245.0L / 486.0L, (265.0L - 100.0L * d) / 1458.0L,
+                      25.0L / 729.0L, 0.0L};
+    auto dot = [&](const LD *u, const LD *v) {
+        LD s = 0.0L;
+        for (int o = 0; o < 5; ++o) s += m[o] * u[o] * v[o];
+        return s;
+    };
+    // subtract from u its component along a (a != 0)
+    auto remove = [&](LD *u, const LD *a) {
+        const LD c = dot(u, a) / dot(a, a);
+        for (int o = 0; o < 5; ++o) u[o] -= c * a[o];
+    };
+    // the norm of the basic rule as the library evaluates it
+    LD n7 = 0.0L;
+    for (int o = 0; o < 5; ++o) n7 += m[o] * (LD)w7d[o] * (LD)w7d[o];
+    n7 = std::sqrt(n7);
+    auto scale_to = [&](LD *u) {
+        const LD c = n7 / std::sqrt(dot(u, u));
+        for (int o = 0; o < 5; ++o) u[o] *= c;
+    };
+    LD g0[5], a[5], b[5], c[5], e[5];
+    for (int o = 0; o < 5; ++o) {
+        // share of the orbit's points with a non-zero x1 (and x2)
+        const LD on1 = o == 0 ? 0.0L : (o <= 2 ? 1.0L / d : (o == 3 ? 2.0L / d : 1.0L));
+        const LD on12 = o == 3 ? 2.0L / (d * (d - 1.0L)) : (o == 4 ? 1.0L : 0.0L);
+        g0[o] = 1.0L;
+        a[o] = w7[o] - w5[o];
+        e[o] = on1 * s2[o];
+        b[o] = on1 * s2[o] * s2[o];
+        c[o] = on12 * s2[o] * s2[o];
+    }
+    // each projection twice (the second pass removes what the first left
+    // through rounding)
+    for (int pass = 0; pass < 2; ++pass) remove(e, g0);       // degree 1
+    for (int pass = 0; pass < 2; ++pass) {
+        remove(b, g0);
+        remove(b, e);
+    }
+    for (int pass = 0; pass < 2; ++pass) {                     // degree 3
+        remove(c, g0);
+        remove(c, e);
+        remove(c, b);
+    }
+    scale_to(a);
+    scale_to(b);
+    scale_to(c);
+    scale_to(e);
+    for (int o = 0; o < 5; ++o) {
+        nul[0][o] = (double)a[o];
+        nul[1][o] = (double)b[o];
+        nul[2][o] = (double)c[o];
+        nul[3][o] = (double)e[o];
+    }
+}
+
+Rule make_rule(int d, int err_rule) {
     Rule R{};
     const double D9 = 19683.0;
     R.lam2 = std::sqrt(9.0 / 70.0);
@@ -174,6 +252,16 @@ Rule make_rule(int d) {
     for (int k = 0; k < 5; ++k) {
         R.w7[k] = w7[k];
         R.wn[k] = w7[k] - w5[k];
+    }
+    R.err_rule = err_rule;
+    if (err_rule == PG_ERR_NULL4) {
+        // twice max(1, L_d), L_d = sup over directions a of the limit
+        // (|a| -> 0) of the degree-7 error over r^2 e3 for exp(a.x):
+        // 0.050, 0.354, 1.896, 7.038, 8.724, 10.17, 12.03, 14.28, 16.87
+        static const double kappa[PG_DIM_MAX + 1] = {
+            0.0, 0.0, 2.0, 2.0, 3.8, 15.0, 18.0, 21.0, 25.0, 29.0, 34.0};
+        make_null_rules(d, w7, R.nul);
+        R.kappa = kappa[d];
     }
     return R;
 }
@@ -543,7 +631,15 @@ const char *pg_last_error(const pg_context *ctx) {
 int pg_evaluate(pg_context *ctx, const pg_integrand *f, int64_t n,
                 const double *lo, const double *w, int64_t ld, double *V,
                 double *E, uint8_t *K) {
+    return pg_evaluate_rule(ctx, f, PG_ERR_RAW, n, lo, w, ld, V, E, K);
+}
+
+int pg_evaluate_rule(pg_context *ctx, const pg_integrand *f, int error_rule,
+                     int64_t n, const double *lo, const double *w, int64_t ld,
+                     double *V, double *E, uint8_t *K) {
     if (!ctx) return PG_EINVAL;
+    if (error_rule != PG_ERR_RAW && error_rule != PG_ERR_NULL4)
+        return fail(ctx, PG_EINVAL, "unknown error rule %d", error_rule);
     FParams P;
     int rc = make_params(ctx, f, &P);
     if (rc) return rc;
@@ -552,7 +648,7 @@ int pg_evaluate(pg_context *ctx, const pg_integrand *f, int64_t n,
     if (!lo || !w || !V || !E || !K)
         return fail(ctx, PG_EINVAL, "NULL array");
     HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
-    const Rule R = make_rule(f->dim);
+    const Rule R = make_rule(f->dim, error_rule);
     HIP_OR_FAIL(ctx, launch_evaluate(ctx->stream, f->family, f->dim, P, R, n,
                                      lo, w, ld, V, E, K,
                                      eval_waves(f->dim, n)));
@@ -705,6 +801,8 @@ int pg_integrate(pg_context *ctx, const pg_integrand *f, const double *lo,
         return fail(ctx, PG_EINVAL, "no positive tolerance");
     if (o.init_splits < 1) return fail(ctx, PG_EINVAL, "init_splits < 1");
     if (o.max_iters < 1) return fail(ctx, PG_EINVAL, "max_iters < 1");
+    if (o.error_rule != PG_ERR_RAW && o.error_rule != PG_ERR_NULL4)
+        return fail(ctx, PG_EINVAL, "unknown error rule %d", o.error_rule);
     const int64_t cap = o.max_regions > 0 ? o.max_regions : ctx->cap;
     if (cap > ctx->cap)
         return fail(ctx, PG_ENOMEM, "max_regions %lld above the capacity %lld",
@@ -717,7 +815,7 @@ int pg_integrate(pg_context *ctx, const pg_integrand *f, const double *lo,
                         o.init_splits, d, (long long)cap);
     }
     HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
-    const Rule R = make_rule(d);
+    const Rule R = make_rule(d, o.error_rule);
     const double tau = o.rel_tol;
     const int64_t ld = ctx->cap;
     hipStream_t st = ctx->stream;
@@ -972,6 +1070,8 @@ static int run_batch(pg_context *ctx, int family, int dim, int B,
             return fail(ctx, PG_EINVAL, "empty or infinite range on axis %d", k);
     if (o.init_splits < 1 || o.max_iters < 1)
         return fail(ctx, PG_EINVAL, "init_splits / max_iters < 1");
+    if (o.error_rule != PG_ERR_RAW && o.error_rule != PG_ERR_NULL4)
+        return fail(ctx, PG_EINVAL, "unknown error rule %d", o.error_rule);
     const int64_t cap = o.max_regions > 0 ? o.max_regions : ctx->cap;
     if (cap > ctx->cap)
         return fail(ctx, PG_ENOMEM, "max_regions %lld above the capacity %lld",
@@ -987,7 +1087,7 @@ static int run_batch(pg_context *ctx, int family, int dim, int B,
                               (int64_t)BATCH_MAX_SLOTS}));
     HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
-    const Rule R = make_rule(d);
+    const Rule R = make_rule(d, o.error_rule);
     const int64_t ld = ctx->cap;
     double a[PG_DIM_MAX], width[PG_DIM_MAX];
     for (int k = 0; k < d; ++k) {

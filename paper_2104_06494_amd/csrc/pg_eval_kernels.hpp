@@ -96,6 +96,19 @@ __device__ __forceinline__ double integrand(const double *x, const FParams &P) {
     }
 }
 
+// Error of a region from its null-rule magnitudes (PG_ERR_NULL4; see
+// NULL_KAPPA): a ratio is 0 when its numerator is 0, infinite when only
+// its denominator is.
+__device__ __forceinline__ double null4_error(double kappa, double e5,
+                                              double e3, double e1) {
+    const double inf = __builtin_inf();
+    const double r31 = e3 == 0.0 ? 0.0 : (e1 == 0.0 ? inf : e3 / e1);
+    const double r53 = e5 == 0.0 ? 0.0 : (e3 == 0.0 ? inf : e5 / e3);
+    const double r = fmax(r31, r53);
+    if (r <= NULL_RC) return kappa * r * r * e3;
+    return fmax(fmax(e5, e3), e1);
+}
+
 // ---------------------------------------------------------------------------
 // EVALUATE
 // ---------------------------------------------------------------------------
@@ -233,7 +246,19 @@ k_evaluate(const FParams P, const Rule R, int64_t n,
         const double sn = R.wn[0] * fc + R.wn[1] * S2 + R.wn[2] * S3 +
                           R.wn[3] * S4 + R.wn[4] * S5;
         V[r0] = vol * s7;
-        E[r0] = fabs(vol * sn);
+        if (R.err_rule == PG_ERR_NULL4) {
+            double nv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                nv[q] = vol * (R.nul[q][0] * fc + R.nul[q][1] * S2 +
+                               R.nul[q][2] * S3 + R.nul[q][3] * S4 +
+                               R.nul[q][4] * S5);
+            E[r0] = null4_error(R.kappa, fabs(nv[0]),
+                                sqrt(0.5 * (nv[1] * nv[1] + nv[2] * nv[2])),
+                                fabs(nv[3]));
+        } else {
+            E[r0] = fabs(vol * sn);
+        }
         double dk[D], dmax = 0.0;
 #pragma unroll
         for (int k = 0; k < D; ++k) {

@@ -42,11 +42,27 @@ struct FParams {
 
 // Per-dimension rule constants: generators lambda2..5 and the weights of
 // the degree-7 rule (w7) and of the null rule (wn = w7 - w5) per orbit.
+// With err_rule = PG_ERR_NULL4 the error comes from the four null rules of
+// the same points, nul[0] (degree 5), nul[1], nul[2] (degree 3) and nul[3]
+// (degree 1), per-orbit weights with the degree-7 rule's norm.
 struct Rule {
     double lam2, lam3, lam4, lam5;
     double w7[5];
     double wn[5];
+    double nul[4][5];
+    double kappa;
+    int err_rule;
 };
+
+// Four-null-rule error (Section 3.2's comparison with four further
+// rules): from e5 = |N1|, e3 = rms(N2, N3), e1 = |N4|, which for a smooth
+// integrand shrink by a factor r ~ (h f-scale)^2 per two degrees while the
+// degree-7 rule errs by ~h^8 (about r^2 e3 by the same decay), the
+// estimate is kappa_d r^2 e3 when r = max(e3 / e1, e5 / e3) <= NULL_RC,
+// else the largest of the three. kappa_d (Rule::kappa) is twice the larger
+// of 1 and the worst limit ratio of true error to r^2 e3 over
+// f = exp(a.x), rounded up to two digits.
+constexpr double NULL_RC = 0.5;
 
 // Segment geometry of a list of n regions (paired: two halves of n/2).
 __host__ __device__ inline int64_t seg_count(int64_t n, int paired) {

@@ -74,9 +74,10 @@ SUITE_MUTANTS = {
 
 # mistakes in the four null rules and the estimate built on them
 NULL4_MUTANTS = {
-    "null_pair_multiplicity": ("m[3] = 2.0 * d * (d - 1);", "m[3] = 1.0 * d * (d - 1);"),
-    "null_pair_mean": ("g[1][3] = 2.0 * L2[3] / d;", "g[1][3] = L2[3] / d;"),
-    "null_degree_swap": ("nul[1][o] = n7 * q[2][o];", "nul[1][o] = n7 * q[1][o];"),
+    "null_pair_multiplicity": ("m[3] = 2.0L * d * (d - 1);", "m[3] = 1.0L * d * (d - 1);"),
+    "null_pair_mean": ("g[1][3] = 2.0L * L2[3] / d;", "g[1][3] = L2[3] / d;"),
+    "null_degree_swap": ("nul[1][o] = (double)(n7 * q[2][o]);",
+                         "nul[1][o] = (double)(n7 * q[1][o]);"),
     "null_rms_half": ("e3 = sqrt((nv[1] * nv[1] + nv[2] * nv[2]) / 2.0);",
                       "e3 = sqrt(nv[1] * nv[1] + nv[2] * nv[2]);"),
     "null_r_power": ("return kappa * r * r * e3;", "return kappa * r * e3;"),
