@@ -18,7 +18,9 @@ Prints one JSON line:
 Other modes feed the profiles: --mode integrand (integrand values only, to
 count one evaluation's FP64 operations with rocprofv3 counters) and
 --mode copy (a plain device copy of known size, to scale FETCH_SIZE /
-WRITE_SIZE).
+WRITE_SIZE). Experiments: --mode suite (the paper's f1..f8 over its
+tolerance sweep, --error-rule raw or null4) and --mode errors (the two
+region error estimates on peaked integrals with closed forms).
 """
 import argparse
 import json
@@ -38,7 +40,7 @@ F_GAUSSIAN_D5 = 47.0
 # HBM bytes per evaluate launch of this workload from FETCH_SIZE / WRITE_SIZE
 # (scaled by a plain copy), valid only for the kernel source they were taken
 # on (first 16 hex digits of its sha256); reported as null otherwise.
-EVAL_TRAFFIC = {"bytes_per_launch": 37796192.0, "kernel_sha256": "7274ebe465c30795",
+EVAL_TRAFFIC = {"bytes_per_launch": 37810118.1, "kernel_sha256": "f31324e62b294cc9",
                 "profile": "profiles/evaluate_gaussian_d5_counters.txt"}
 # MI355X FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz.
 PEAK_FP64_TFLOPS = 78.6
@@ -267,14 +269,17 @@ def suite_mode(args):
         if args.suite_only and not name.startswith(args.suite_only):
             continue
         ex = cf.exact(wl.family, wl.params, wl.d)
-        ctx.integrate_workload(wl, rel_tol=tols[0], max_regions=0, threshold_filter=thr)
+        ctx.integrate_workload(wl, rel_tol=tols[0], max_regions=0, threshold_filter=thr,
+                               error_rule=args.error_rule)
         for tol in tols:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            r = ctx.integrate_workload(wl, rel_tol=tol, max_regions=0, threshold_filter=thr)
+            r = ctx.integrate_workload(wl, rel_tol=tol, max_regions=0, threshold_filter=thr,
+                                       error_rule=args.error_rule)
             torch.cuda.synchronize()
             ms = 1e3 * (time.perf_counter() - t0)
             print(json.dumps({"mode": "suite", "integrand": name, "rel_tol": tol,
+                              "error_rule": args.error_rule,
                               "status": r.status_name, "estimate": r.estimate,
                               "true_rel_err": abs(r.estimate - ex) / abs(ex),
                               "est_rel_err": r.error / abs(r.estimate),
@@ -284,6 +289,48 @@ def suite_mode(args):
                               r.fevals / (ms * 1e-3)}), flush=True)
             if r.status_name != "OK":
                 break
+    ctx.close()
+
+
+def errors_mode(args):
+    """The two region error estimates (|R7 - R5| and the four null rules)
+    on sharply peaked integrals with closed forms, through the batched
+    driver: per family, dimension, tolerance and estimate, the share of
+    runs that converge, of runs whose reported error bounds the true error
+    (every run, whatever its status), of converged runs that meet the
+    tolerance, and the regions and time spent. One JSON line each."""
+    import numpy as np
+    import torch
+    import paper_2104_06494_amd as pg
+    import workloads as W
+    from workloads import closed_forms as cf
+
+    torch.cuda.set_device(0)
+    ctx = pg.Context(capacity=args.batch_slots << 20, dim_max=8)
+    for family, d in (("gaussian", 5), ("gaussian", 8), ("product_peak", 5),
+                      ("product_peak", 8)):
+        wl = W.peaked_batch(family, d, B=args.errors_batch)
+        exact = np.array([cf.exact(family, p, d) for p in wl.params])
+        for tol in (1e-3, 1e-4, 1e-5, 1e-6):
+            for rule in ("raw", "null4"):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                res = ctx.integrate_batch(family, d, wl.params, tol, init_splits=2,
+                                          max_regions=wl.max_regions, error_rule=rule)
+                torch.cuda.synchronize()
+                ms = 1e3 * (time.perf_counter() - t0)
+                est = np.array([r.estimate for r in res])
+                err = np.array([r.error for r in res])
+                ok = np.array([r.status_name == "OK" for r in res])
+                true = np.abs(est - exact)
+                print(json.dumps({
+                    "mode": "errors", "workload": wl.name, "rel_tol": tol,
+                    "error_rule": rule, "B": wl.B, "converged": int(ok.sum()),
+                    "error_bounds_true": int((true <= err).sum()),
+                    "converged_meet_tol": int((true[ok] <= tol * np.abs(exact[ok])).sum()),
+                    "median_true_over_tol": float(np.median(true / (tol * np.abs(exact)))),
+                    "regions_evaluated": int(sum(r.regions_evaluated for r in res)),
+                    "ms": ms}), flush=True)
     ctx.close()
 
 
@@ -343,7 +390,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", choices=["headline", "batched", "adjoint", "suite",
-                                       "integrand", "copy"],
+                                       "errors", "integrand", "copy"],
                     default="headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
@@ -358,6 +405,10 @@ def main():
                     help="regions of the context the suite sweep runs in")
     ap.add_argument("--suite-only", default="",
                     help="suite integrands whose name starts with this only")
+    ap.add_argument("--error-rule", default="raw", choices=["raw", "null4"],
+                    help="region error estimate of the suite sweep")
+    ap.add_argument("--errors-batch", type=int, default=128,
+                    help="integrals per family and tolerance in --mode errors")
     ap.add_argument("--batch-slots", type=int, default=64,
                     help="integrals in flight in the batched run (each "
                          "reserves 2^21 regions of workspace)")
@@ -368,7 +419,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     {"headline": headline, "batched": batched_mode, "adjoint": adjoint_mode,
-     "suite": suite_mode, "integrand": integrand_mode,
+     "suite": suite_mode, "errors": errors_mode, "integrand": integrand_mode,
      "copy": copy_mode}[args.mode](args)
 
 

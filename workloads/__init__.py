@@ -269,6 +269,20 @@ def gaussian_grad_d6(B: int = 256, seed: int = 5,
                          np.full(B, 1e-20), init_splits=2, max_regions=1 << 22)
 
 
+def peaked_batch(family: str, d: int, B: int = 128, seed: int = 6,
+                 rel_tol: float = 1e-4) -> BatchWorkload:
+    """B sharply peaked integrals for comparing error estimates: Gaussians
+    (a ~ U[10, 30]) or product peaks (a ~ U[5, 20]), peak centres
+    u ~ U[0.2, 0.8] per axis, 2^d initial grid, cap 2^20 regions each."""
+    rng = np.random.default_rng(seed)
+    lo_a, hi_a = (10.0, 30.0) if family == "gaussian" else (5.0, 20.0)
+    a = rng.uniform(lo_a, hi_a, size=(B, d))
+    u = rng.uniform(0.2, 0.8, size=(B, d))
+    return BatchWorkload(f"{family}_peaked_d{d}", family, d,
+                         np.concatenate([a, u], axis=1), np.full(B, rel_tol),
+                         np.full(B, 1e-20), init_splits=2, max_regions=1 << 20)
+
+
 def random_boxes(d: int, n: int, seed: int, lo=0.0, hi=1.0,
                  dyadic_bits: int = 0):
     """n random axis-aligned boxes inside [lo, hi]^d, as SoA arrays
