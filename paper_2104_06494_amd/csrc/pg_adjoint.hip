@@ -64,7 +64,7 @@ __device__ __forceinline__ void point_grad(const double (&x)[D],
             const double at = P.p[k] * t[k];
             s = fma(at, at, s);
         }
-        const double wf = wgt * exp(-s);
+        const double wf = wgt * exp_nonpos(-s);
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             const double wt = wf * t[k];

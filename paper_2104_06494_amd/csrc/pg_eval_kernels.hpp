@@ -41,7 +41,7 @@ __device__ __forceinline__ double integrand(const double *x, const FParams &P) {
             const double t = x[k] - P.p[D + k];
             s = fma(P.p[k] * t, t, s);
         }
-        return exp(-s);
+        return exp_nonpos(-s);
     } else if constexpr (FAM == PG_OSCILLATORY) {
         double s = P.p[D];
 #pragma unroll
@@ -67,7 +67,7 @@ __device__ __forceinline__ double integrand(const double *x, const FParams &P) {
         double s = 0.0;
 #pragma unroll
         for (int k = 0; k < D; ++k) s = fma(P.p[k], fabs(x[k] - P.p[D + k]), s);
-        return exp(-s);
+        return exp_nonpos(-s);
     } else if constexpr (FAM == PG_DISCONTINUOUS) {
         double s = 0.0;
         bool in = true;

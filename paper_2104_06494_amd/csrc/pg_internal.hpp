@@ -36,6 +36,38 @@ constexpr int SCAN_THREADS = 1024;
 //  discontinuous: p[k] = a_k,   p[d+k] = c_k
 //  box:          p[0] = p, p[1] = 0 (integer p, p[2] = p), 1 (p = p[2] +
 //                1/2), 2 (other p: pow)
+// e^x for x <= 0 (the Gaussian's and the C0 integrand's exponent), no
+// special cases: Cody-Waite reduction x = n ln2 + r, |r| <= ln2/2, with ln 2
+// split into two doubles and the reduction done by two FMAs; e^r by the
+// degree-11 polynomial interpolating e^r at the 12 Chebyshev points of
+// [-ln2/2, ln2/2] (coefficients from 60-digit arithmetic rounded to double;
+// the polynomial's relative error is 1.7e-17), Horner's rule; then 2^n by
+// ldexp, which underflows gradually and reaches 0 below -745 without a
+// test. Largest error 0.91 ulp on 2e5 points of [-745, 0] against a
+// 40-digit reference. NaN in, NaN out; x = -inf (an exponent that
+// overflowed) gives NaN.
+__device__ __forceinline__ double exp_nonpos(double x) {
+    constexpr double LOG2E = 1.4426950408889634;      // RN(1 / ln 2)
+    constexpr double LN2_HI = 0.6931471805599453;     // RN(ln 2)
+    constexpr double LN2_LO = 2.3190468138462996e-17; // RN(ln 2 - LN2_HI)
+    const double n = rint(x * LOG2E);
+    double r = fma(-n, LN2_HI, x);
+    r = fma(-n, LN2_LO, r);
+    double q = 2.5110037605963777e-08;
+    q = fma(q, r, 2.763263963904103e-07);
+    q = fma(q, r, 2.755724091857897e-06);
+    q = fma(q, r, 2.4801485482328494e-05);
+    q = fma(q, r, 0.00019841269890047113);
+    q = fma(q, r, 0.0013888888952314775);
+    q = fma(q, r, 0.008333333333319601);
+    q = fma(q, r, 0.0416666666664881);
+    q = fma(q, r, 0.1666666666666668);
+    q = fma(q, r, 0.5000000000000019);
+    q = fma(q, r, 1.0);
+    q = fma(q, r, 1.0);
+    return ldexp(q, (int)n);
+}
+
 struct FParams {
     double p[2 * PG_DIM_MAX + 2];
 };

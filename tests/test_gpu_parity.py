@@ -66,6 +66,27 @@ def test_integrand_values(ctx, family, d):
     np.testing.assert_allclose(y, ref, rtol=2e-13, atol=0)
 
 
+def test_gaussian_exponential_to_two_ulps(ctx):
+    """The Gaussian's e^-s over the whole range s in [0, 745] (and beyond,
+    where it is 0), against the oracle (glibc): within 2 ulps plus the
+    rounding of s itself (|s| ulps of e^-s), denormals by their spacing."""
+    _say("integrand exp range")
+    d = 2
+    p = np.array([1.0, 1.0, 0.0, 0.0])                 # f = exp(-(x1^2 + x2^2))
+    rng = np.random.default_rng(17)
+    r = np.concatenate([rng.uniform(0, 2, 4000), rng.uniform(0, 27.4, 4000),
+                        [0.0, 27.3, 27.5, 30.0]])
+    ang = rng.uniform(0, np.pi / 2, r.size)
+    x = np.stack([r * np.cos(ang), r * np.sin(ang)])
+    y = ctx.integrand_values("gaussian", p, _dev(x)).cpu().numpy()
+    ref = np.array([oracle.f("gaussian", p, x[:, i]) for i in range(x.shape[1])])
+    s = (x ** 2).sum(axis=0)
+    ulp = np.spacing(np.maximum(np.abs(ref), np.finfo(float).tiny))
+    tol = (2.0 + 2.0 * s) * ulp + 2 * np.spacing(0.0)
+    assert np.all(np.abs(y - ref) <= tol), np.max(np.abs(y - ref) / ulp)
+    assert y[-1] == 0.0 and ref[-1] == 0.0
+
+
 # ---------------------------------------------------------------------------
 # EVALUATE
 # ---------------------------------------------------------------------------
