@@ -110,7 +110,10 @@ typedef struct {
                                  0: off, for sign-changing integrands (3.5.1) */
     int threshold_filter;     /* 1: threshold search on (Algorithm 3); 0: off */
     int64_t max_regions;      /* cap on the live list; 0: context capacity */
-    int timing;               /* 1: time each phase with HIP events */
+    int timing;               /* HIP events on the stream: 1 around each
+                                 EVALUATE launch (phase_ms[0] only), 2
+                                 around every phase; 0: none (each event
+                                 costs the run a few microseconds) */
     const char *trace_path;   /* non-NULL: write the decision trace (below) */
     int error_rule;           /* pg_error_rule */
 } pg_options;
@@ -132,7 +135,9 @@ typedef struct {
     int64_t threshold_trials;
     double phase_ms[4];       /* with timing: evaluate, post-processing
                                  (two-level, classify, sums), threshold
-                                 search, filter + split (Section 4.3.2) */
+                                 search and the host's decisions, filter +
+                                 split (Section 4.3.2); level 1 fills only
+                                 the first */
     int64_t eval_launches;    /* number of evaluate kernel launches */
 } pg_result;
 

@@ -156,7 +156,9 @@ class Context:
         o.rel_tol, o.abs_tol = float(rel_tol), float(abs_tol)
         o.init_splits, o.max_iters = int(init_splits), int(max_iters)
         o.relerr_filter, o.threshold_filter = int(relerr_filter), int(threshold_filter)
-        o.max_regions, o.timing = int(max_regions), int(bool(timing))
+        # timing: False / 0 none, 1 the EVALUATE launches, True / 2 every phase
+        o.max_regions = int(max_regions)
+        o.timing = 2 if timing is True else int(timing)
         o.trace_path = trace_path.encode() if trace_path else None
         o.error_rule = _error_rule(error_rule)
         r = L.Result()

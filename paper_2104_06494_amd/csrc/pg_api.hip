@@ -833,8 +833,9 @@ int pg_integrate(pg_context *ctx, const pg_integrand *f, const double *lo,
         std::fwrite(hd, 4, 2, tr);
         std::fwrite(zero, 8, 2, tr);
     }
-    // timing events: 5 per iteration
-    const bool timing = o.timing != 0;
+    // timing events: 5 per iteration (level 1 records only the two around
+    // EVALUATE, level 2 all five)
+    const int timing = o.timing < 0 ? 0 : o.timing;
     if (timing) {
         const size_t need = 5 * (size_t)o.max_iters;
         while (ctx->events.size() < need) {
@@ -892,7 +893,7 @@ int pg_integrate(pg_context *ctx, const pg_integrand *f, const double *lo,
                                  o.relerr_filter, ctx->A, ctx->part));
         const int64_t nseg = seg_count(n, paired);
         RUN_FAIL(launch_reduce_scan(st, nseg, ctx->part, ctx->off, ctx->dtot));
-        if (timing) RUN_FAIL(hipEventRecord(ev[2], st));
+        if (timing > 1) RUN_FAIL(hipEventRecord(ev[2], st));
         Totals T;
         RUN_RC(sync_tot(ctx, &T));
         const double v = T.v, e = T.e;
@@ -945,7 +946,7 @@ int pg_integrate(pg_context *ctx, const pg_integrand *f, const double *lo,
                 rec.terminal = status;
             }
         }
-        if (timing) RUN_FAIL(hipEventRecord(ev[3], st));
+        if (timing > 1) RUN_FAIL(hipEventRecord(ev[3], st));
         if (rec.terminal < 0) {
             prev_vtot = v_tot;
             if (n_act == 0) {
@@ -976,7 +977,7 @@ int pg_integrate(pg_context *ctx, const pg_integrand *f, const double *lo,
             std::fwrite(hA.data(), 1, n, tr);
         }
         if (rec.terminal >= 0) {
-            if (timing) RUN_FAIL(hipEventRecord(ev[4], st));
+            if (timing > 1) RUN_FAIL(hipEventRecord(ev[4], st));
             break;
         }
         v_f = v - av + v_f;
@@ -986,7 +987,7 @@ int pg_integrate(pg_context *ctx, const pg_integrand *f, const double *lo,
                                       ctx->K, ctx->lo[cur], ctx->w[cur], ld,
                                       ctx->off, n_act, ctx->lo[1 - cur],
                                       ctx->w[1 - cur], ld, ctx->Vp));
-        if (timing) RUN_FAIL(hipEventRecord(ev[4], st));
+        if (timing > 1) RUN_FAIL(hipEventRecord(ev[4], st));
         cur = 1 - cur;
         n = 2 * n_act;
         res.peak_regions = std::max<int64_t>(res.peak_regions, n);
@@ -999,7 +1000,7 @@ int pg_integrate(pg_context *ctx, const pg_integrand *f, const double *lo,
         for (int q = 0; q < it; ++q) {
             hipEvent_t *ev = &ctx->events[5 * q];
             float ms;
-            for (int ph = 0; ph < 4; ++ph) {
+            for (int ph = 0; ph < (timing > 1 ? 4 : 1); ++ph) {
                 if (hipEventElapsedTime(&ms, ev[ph], ev[ph + 1]) == hipSuccess)
                     res.phase_ms[ph] += ms;
             }
