@@ -38,6 +38,11 @@ struct pg_context {
     double *search_part = nullptr;
     Totals *dtot = nullptr, *htot = nullptr;
     SearchState *dstate = nullptr, *hstate = nullptr;
+    // device addresses of htot / hstate (pinned host memory mapped into
+    // the device's address space): kernels leave the values the host reads
+    // there directly, so no copy is queued before a wait
+    Totals *htot_dev = nullptr;
+    SearchState *hstate_dev = nullptr;
     // many-integral runs
     uint32_t *inst[2] = {nullptr, nullptr};
     BInst *b_inst = nullptr, *hb_inst = nullptr;
@@ -400,6 +405,15 @@ int sync_tot(pg_context *ctx, Totals *out) {
     return PG_OK;
 }
 
+// The totals a reduce launched with host_tot = ctx->htot_dev left in the
+// mapped host copy: wait for the stream (the kernel's writes to host memory
+// are visible once it has completed), then read them.
+int wait_tot(pg_context *ctx, Totals *out) {
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+    *out = *ctx->htot;
+    return PG_OK;
+}
+
 // THRESHOLD-CLASSIFY (Algorithm 3) on the list (E, A_rel) of n regions; its
 // state lives on the device (see k_trial_walk). Passes are queued in
 // batches of 3, 5 and 8 (most searches end in the first) and the host
@@ -448,15 +462,16 @@ int search(pg_context *ctx, int64_t n, const double *E, const uint8_t *A_rel,
             HIP_OR_FAIL(ctx, launch_seg_count(st, n, count->paired, 0.0,
                                               count->V, E, A_rel, ctx->dstate,
                                               ctx->part));
+            // the totals and the search state go straight to the host
             HIP_OR_FAIL(ctx, launch_reduce_scan(st, seg_count(n, count->paired),
                                                 ctx->part, ctx->off,
-                                                ctx->dtot));
-            HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->htot, ctx->dtot, sizeof(Totals),
+                                                ctx->dtot, ctx->htot_dev,
+                                                ctx->dstate, ctx->hstate_dev));
+        } else {
+            HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->hstate, ctx->dstate,
+                                            sizeof(SearchState),
                                             hipMemcpyDeviceToHost, st));
         }
-        HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->hstate, ctx->dstate,
-                                        sizeof(SearchState),
-                                        hipMemcpyDeviceToHost, st));
         HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
         if (ctx->hstate->done) break;
     }
@@ -532,8 +547,15 @@ int pg_context_create(int device, int dim_max, int64_t capacity,
         ctx->own_ws = true;
     }
     ctx->stream = (hipStream_t)stream;      // NULL: the null stream
-    if (hipHostMalloc((void **)&ctx->htot, sizeof(Totals), 0) != hipSuccess ||
-        hipHostMalloc((void **)&ctx->hstate, sizeof(SearchState), 0) !=
+    if (hipHostMalloc((void **)&ctx->htot, sizeof(Totals),
+                      hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostMalloc((void **)&ctx->hstate, sizeof(SearchState),
+                      hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostGetDevicePointer((void **)&ctx->htot_dev, ctx->htot, 0) !=
+            hipSuccess ||
+        hipHostGetDevicePointer((void **)&ctx->hstate_dev, ctx->hstate, 0) !=
             hipSuccess ||
         hipHostMalloc((void **)&ctx->hb_inst,
                       sizeof(BInst) * INST_STAGES * BATCH_MAX_SLOTS,
@@ -892,10 +914,11 @@ int pg_integrate(pg_context *ctx, const pg_integrand *f, const double *lo,
         RUN_FAIL(launch_classify(st, n, paired, ctx->V, ctx->E, ctx->Vp, tau,
                                  o.relerr_filter, ctx->A, ctx->part));
         const int64_t nseg = seg_count(n, paired);
-        RUN_FAIL(launch_reduce_scan(st, nseg, ctx->part, ctx->off, ctx->dtot));
+        RUN_FAIL(launch_reduce_scan(st, nseg, ctx->part, ctx->off, ctx->dtot,
+                                    ctx->htot_dev));
         if (timing > 1) RUN_FAIL(hipEventRecord(ev[2], st));
         Totals T;
-        RUN_RC(sync_tot(ctx, &T));
+        RUN_RC(wait_tot(ctx, &T));
         const double v = T.v, e = T.e;
         v_tot = v + v_f;
         e_tot = e + e_f;

@@ -293,8 +293,13 @@ hipError_t launch_seg_count(hipStream_t st, int64_t n, int paired, double t,
                             const double *V, const double *E,
                             const uint8_t *A_rel, const SearchState *S,
                             SegPartials part);
+// host_tot / host_state (device addresses of mapped pinned host memory, or
+// NULL): the kernel also leaves there the totals and a copy of *state.
 hipError_t launch_reduce_scan(hipStream_t st, int64_t nseg, SegPartials part,
-                              uint32_t *offsets, Totals *tot);
+                              uint32_t *offsets, Totals *tot,
+                              Totals *host_tot = nullptr,
+                              const SearchState *state = nullptr,
+                              SearchState *host_state = nullptr);
 hipError_t launch_search_init(hipStream_t st, SearchState *S, int64_t n,
                               double e_it, double allowance, int mem,
                               const Totals *minmax);

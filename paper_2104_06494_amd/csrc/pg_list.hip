@@ -52,8 +52,16 @@ k_seg_count(int64_t n, int paired, double t, const double *__restrict__ V,
 // Single-block totals of the segment partials + exclusive scan of the counts
 __global__ void __launch_bounds__(SCAN_THREADS)
 k_reduce_scan(int64_t nseg, SegPartials part, uint32_t *__restrict__ offsets,
-              Totals *__restrict__ tot) {
+              Totals *__restrict__ tot, Totals *__restrict__ host_tot,
+              const SearchState *__restrict__ state,
+              SearchState *__restrict__ host_state) {
     reduce_scan_segments(0, nseg, part, offsets, tot);
+    // the host's copies (pinned host memory mapped into the device's
+    // address space), so that no copy has to be queued behind this kernel
+    if (threadIdx.x == 0) {
+        if (host_tot) *host_tot = *tot;
+        if (host_state) *host_state = *state;
+    }
 }
 
 __global__ void k_search_init(SearchState *__restrict__ S, int64_t n,
@@ -254,9 +262,11 @@ hipError_t launch_seg_count(hipStream_t st, int64_t n, int paired, double t,
 }
 
 hipError_t launch_reduce_scan(hipStream_t st, int64_t nseg, SegPartials part,
-                              uint32_t *offsets, Totals *tot) {
+                              uint32_t *offsets, Totals *tot, Totals *host_tot,
+                              const SearchState *state,
+                              SearchState *host_state) {
     hipLaunchKernelGGL(k_reduce_scan, dim3(1), dim3(SCAN_THREADS), 0, st, nseg,
-                       part, offsets, tot);
+                       part, offsets, tot, host_tot, state, host_state);
     return hipGetLastError();
 }
 
