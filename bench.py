@@ -40,8 +40,8 @@ F_GAUSSIAN_D5 = 47.0
 # HBM bytes per evaluate launch of this workload from FETCH_SIZE / WRITE_SIZE
 # (scaled by a plain copy), valid only for the kernel source they were taken
 # on (first 16 hex digits of the sha256 of pg_eval_kernels.hpp followed by
-# pg_internal.hpp); reported as null otherwise.
-EVAL_TRAFFIC = {"bytes_per_launch": 37762550.9, "kernel_sha256": "1652cccf9ea551d5",
+# pg_eval_defs.hpp); reported as null otherwise.
+EVAL_TRAFFIC = {"bytes_per_launch": 37762550.9, "kernel_sha256": "489697912347979c",
                 "profile": "profiles/evaluate_gaussian_d5_counters.txt"}
 # MI355X FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz.
 PEAK_FP64_TFLOPS = 78.6
@@ -49,10 +49,10 @@ PEAK_FP64_TFLOPS = 78.6
 
 def _kernel_sha():
     """sha256 (16 hex digits) of the evaluate kernel's source: its header and
-    the shared one it includes (rule, parameters, exponential)."""
+    the definitions it is built from (rule, parameters, exponential)."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("pg_eval_kernels.hpp", "pg_internal.hpp"):
+    for name in ("pg_eval_kernels.hpp", "pg_eval_defs.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2104_06494_amd", "csrc", name), "rb").read())
     return h.hexdigest()[:16]
 
