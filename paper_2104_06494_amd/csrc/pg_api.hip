@@ -48,6 +48,7 @@ struct pg_context {
     BInst *b_inst = nullptr, *hb_inst = nullptr;
     SearchState *b_state = nullptr, *hb_state = nullptr;
     Totals *b_tot = nullptr, *hb_tot = nullptr;
+    Totals *hb_tot_dev = nullptr;            // device address of hb_tot
     FParams *b_table = nullptr, *hb_table = nullptr;
     int32_t *b_order = nullptr, *hb_order = nullptr;
     int32_t *b_new = nullptr, *hb_new = nullptr;
@@ -568,7 +569,10 @@ int pg_context_create(int device, int dim_max, int64_t capacity,
         hipHostMalloc((void **)&ctx->hb_state,
                       sizeof(SearchState) * BATCH_MAX_SLOTS, 0) != hipSuccess ||
         hipHostMalloc((void **)&ctx->hb_tot, sizeof(Totals) * BATCH_MAX_SLOTS,
-                      0) != hipSuccess ||
+                      hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostGetDevicePointer((void **)&ctx->hb_tot_dev, ctx->hb_tot, 0) !=
+            hipSuccess ||
         hipHostMalloc((void **)&ctx->hb_table,
                       sizeof(FParams) * BATCH_MAX_SLOTS, 0) != hipSuccess ||
         hipHostMalloc((void **)&ctx->hb_order,
@@ -1273,12 +1277,10 @@ static int run_batch(pg_context *ctx, int family, int dim, int B,
         HIP_OR_FAIL(ctx, launch_batch_classify(st, ncls, ctx->b_cls,
                                                ctx->b_inst, ctx->V, ctx->E,
                                                ctx->Vp, ctx->A, ctx->part));
+        // the slots' totals go straight to the mapped host copy
         HIP_OR_FAIL(ctx, launch_batch_reduce(st, nslots, ctx->b_order,
                                              ctx->b_inst, ctx->part, ctx->off,
-                                             ctx->b_tot));
-        HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->hb_tot, ctx->b_tot,
-                                        sizeof(Totals) * K,
-                                        hipMemcpyDeviceToHost, st));
+                                             ctx->b_tot, ctx->hb_tot_dev));
         HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
         take_git();
         // ---- termination test and threshold triggers, per slot
@@ -1361,12 +1363,10 @@ static int run_batch(pg_context *ctx, int family, int dim, int B,
         HIP_OR_FAIL(ctx, launch_batch_count(st, nseg, ctx->b_segs, ctx->b_inst,
                                             ctx->b_state, ctx->V, ctx->E,
                                             ctx->A, ctx->part));
+        // the slots' totals go straight to the mapped host copy
         HIP_OR_FAIL(ctx, launch_batch_reduce(st, nslots, ctx->b_order,
                                              ctx->b_inst, ctx->part, ctx->off,
-                                             ctx->b_tot));
-        HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->hb_tot, ctx->b_tot,
-                                        sizeof(Totals) * K,
-                                        hipMemcpyDeviceToHost, st));
+                                             ctx->b_tot, ctx->hb_tot_dev));
         HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
         running = 0;
         std::vector<int> next_order;

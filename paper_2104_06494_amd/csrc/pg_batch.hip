@@ -59,10 +59,13 @@ k_batch_classify(const BCls *__restrict__ cls, const BInst *__restrict__ inst,
 __global__ void __launch_bounds__(SCAN_THREADS)
 k_batch_reduce(const int32_t *__restrict__ order,
                const BInst *__restrict__ inst, SegPartials part,
-               uint32_t *__restrict__ offsets, Totals *__restrict__ tot) {
+               uint32_t *__restrict__ offsets, Totals *__restrict__ tot,
+               Totals *__restrict__ host_tot) {
     const int slot = order[blockIdx.x];
     const BInst &I = inst[slot];
     reduce_scan_segments(I.seg0, I.nseg, part, offsets, tot + slot);
+    // the host's copy (mapped pinned host memory), when given
+    if (host_tot && threadIdx.x == 0) host_tot[slot] = tot[slot];
 }
 
 // Threshold trials of every searching slot: block per segment, the sums of
@@ -256,10 +259,10 @@ hipError_t launch_batch_classify(hipStream_t st, int64_t ncls, const BCls *cls,
 hipError_t launch_batch_reduce(hipStream_t st, int nslots,
                                const int32_t *order, const BInst *inst,
                                SegPartials part, uint32_t *offsets,
-                               Totals *tot) {
+                               Totals *tot, Totals *host_tot) {
     if (nslots <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_batch_reduce, dim3(nslots), dim3(SCAN_THREADS), 0, st,
-                       order, inst, part, offsets, tot);
+                       order, inst, part, offsets, tot, host_tot);
     return hipGetLastError();
 }
 

@@ -124,10 +124,12 @@ hipError_t launch_batch_classify(hipStream_t st, int64_t ncls, const BCls *cls,
                                  const BInst *inst, const double *V, double *E,
                                  const double *Vp, uint8_t *A,
                                  SegPartials part);
+// host_tot (device address of mapped pinned host memory, or NULL): each
+// slot's totals are also left there.
 hipError_t launch_batch_reduce(hipStream_t st, int nslots,
                                const int32_t *order, const BInst *inst,
                                SegPartials part, uint32_t *offsets,
-                               Totals *tot);
+                               Totals *tot, Totals *host_tot = nullptr);
 hipError_t launch_batch_search_pass(hipStream_t st, int64_t nseg,
                                     const BSeg *segs, int nslots,
                                     const int32_t *order, const BInst *inst,
