@@ -20,9 +20,11 @@
  *  - Integrands are a family id plus a parameter vector (no function
  *    pointers: the integrand is inlined into the evaluation kernel):
  *      PG_PRODUCT_PEAK  prod_k 1 / (a_k^-2 + (x_k - u_k)^2)  params a[d], u[d]
+ *                       (a_k != 0)
  *      PG_GAUSSIAN      exp(-sum_k a_k^2 (x_k - u_k)^2)      params a[d], u[d]
  *      PG_OSCILLATORY   cos(2 pi u_1 + sum_k a_k x_k)        params a[d], u_1
  *      PG_CORNER_PEAK   (1 + sum_k a_k x_k)^-(d+1)          params a[d]
+ *                       (1 + sum_k a_k x_k > 0 on the box)
  *      PG_MONOMIAL      prod_k x_k^alpha_k                  params alpha[d]
  *      PG_C0            exp(-sum_k a_k |x_k - u_k|)         params a[d], u[d]
  *      PG_DISCONTINUOUS exp(sum_k a_k x_k) if every x_k < c_k, else 0

@@ -76,7 +76,7 @@ __device__ __forceinline__ void point_grad(const double (&x)[D],
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             t[k] = x[k] - P.p[D + k];
-            r[k] = 1.0 / fma(t[k], t[k], P.p[k]);
+            r[k] = rcp_pos(fma(t[k], t[k], P.p[k]));
             f *= r[k];
         }
         const double wf = wgt * f;
@@ -98,7 +98,7 @@ __device__ __forceinline__ void point_grad(const double (&x)[D],
         double s = 1.0;
 #pragma unroll
         for (int k = 0; k < D; ++k) s = fma(P.p[k], x[k], s);
-        const double r = 1.0 / s;
+        const double r = rcp_pos(s);
         double f = r;
 #pragma unroll
         for (int k = 1; k < D + 2; ++k) f *= r;

@@ -46,6 +46,22 @@ __device__ __forceinline__ double exp_nonpos(double x) {
     return ldexp(q, (int)n);
 }
 
+// 1/x for a positive x whose reciprocal is a normal number (the product
+// peak's and the corner peak's denominators, products of terms >= a^-2 and
+// >= 1): the hardware reciprocal estimate refined by two Newton-Raphson
+// steps r <- r + r (1 - x r), each of which squares the relative error, so
+// the result is within an ulp of 1/x; five instructions where the
+// correctly rounded division with its scaling and special cases takes
+// about ten. Outside that range (x <= 0, denormal, or 1/x beyond the
+// largest double) the result is unspecified.
+__device__ __forceinline__ double rcp_pos(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 // Integrand parameters as the kernels take them (by value, in SGPRs):
 //  product peak: p[k] = a_k^-2, p[d+k] = u_k
 //  gaussian:     p[k] = a_k^2,  p[d+k] = u_k

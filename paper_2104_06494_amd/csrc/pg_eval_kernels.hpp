@@ -33,7 +33,7 @@ __device__ __forceinline__ double integrand(const double *x, const FParams &P) {
             const double t = x[k] - P.p[D + k];
             den *= fma(t, t, P.p[k]);
         }
-        return 1.0 / den;
+        return rcp_pos(den);
     } else if constexpr (FAM == PG_GAUSSIAN) {
         double s = 0.0;
 #pragma unroll
@@ -54,7 +54,7 @@ __device__ __forceinline__ double integrand(const double *x, const FParams &P) {
         double pw = s;
 #pragma unroll
         for (int e = 0; e < D; ++e) pw *= s;   // s^(D+1)
-        return 1.0 / pw;
+        return rcp_pos(pw);
     } else if constexpr (FAM == PG_MONOMIAL) {   // test family
         double r = 1.0;
 #pragma unroll

@@ -87,6 +87,24 @@ def test_gaussian_exponential_to_two_ulps(ctx):
     assert y[-1] == 0.0 and ref[-1] == 0.0
 
 
+@pytest.mark.parametrize("family,d", [("product_peak", 3), ("product_peak", 8),
+                                      ("corner_peak", 2), ("corner_peak", 6),
+                                      ("corner_peak", 10)])
+def test_peak_reciprocal_to_a_few_ulps(ctx, family, d):
+    """The peaks' 1/denominator (refined hardware reciprocal) against the
+    oracle's divisions and pow: within the rounding the two sides' different
+    operation orders allow (a few ulps per factor of the product peak, the
+    (d+1)-fold power of the sum's rounding for the corner peak)."""
+    _say("integrand reciprocal", family, d)
+    p = _params(family, d, seed=23)
+    x = np.random.default_rng(40 + d).uniform(0, 1, size=(d, 4000))
+    y = ctx.integrand_values(family, p, _dev(x)).cpu().numpy()
+    ref = np.array([oracle.f(family, p, x[:, i]) for i in range(x.shape[1])])
+    ulps = np.abs(y - ref) / np.spacing(np.abs(ref))
+    bound = 4 * d + 4 if family == "product_peak" else (d + 1) ** 2 + 4
+    assert ulps.max() <= bound, (ulps.max(), bound)
+
+
 # ---------------------------------------------------------------------------
 # EVALUATE
 # ---------------------------------------------------------------------------
