@@ -41,7 +41,7 @@ F_GAUSSIAN_D5 = 47.0
 # (scaled by a plain copy), valid only for the kernel source they were taken
 # on (first 16 hex digits of the sha256 of pg_eval_kernels.hpp followed by
 # pg_eval_defs.hpp); reported as null otherwise.
-EVAL_TRAFFIC = {"bytes_per_launch": 37762550.9, "kernel_sha256": "489697912347979c",
+EVAL_TRAFFIC = {"bytes_per_launch": 37762550.9, "kernel_sha256": "fefbfb583f0bad4d",
                 "profile": "profiles/evaluate_gaussian_d5_counters.txt"}
 # MI355X FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz.
 PEAK_FP64_TFLOPS = 78.6
