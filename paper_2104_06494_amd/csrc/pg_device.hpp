@@ -96,28 +96,48 @@ __device__ inline void classify_segment(int paired, int64_t q0, int64_t q1,
         block_reduce_store(lo_acc, part, s_lo);
         return;
     }
-    for (int64_t q = q0 + threadIdx.x; q < q1; q += LIST_THREADS) {
-        const int64_t ia = a0 + q, ib = b0 + q;
-        const double va = V[ia], vb = V[ib];
-        double ea = E[ia], eb = E[ib];
-        const double delta = fabs(va + vb - Vp[p0 + q]) / 4.0;
-        const double S = ea + eb;
-        if (S > 0.0) {
-            const double g = 1.0 + 2.0 * delta / S;
-            ea = ea * g + delta;
-            eb = eb * g + delta;
-        } else {
-            ea = ea + delta;
-            eb = eb + delta;
+    // in chunks of SEG pairs (a segment is one chunk), PER per thread: every
+    // load of a chunk is issued before the first use; the sums keep the
+    // order of a plain strided loop
+    constexpr int PER = SEG / LIST_THREADS;
+    for (int64_t c0 = q0; c0 < q1; c0 += SEG) {
+        double va[PER], vb[PER], ea[PER], eb[PER], vp[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int64_t q = c0 + threadIdx.x + (int64_t)k * LIST_THREADS;
+            if (q < q1) {
+                va[k] = V[a0 + q];
+                vb[k] = V[b0 + q];
+                ea[k] = E[a0 + q];
+                eb[k] = E[b0 + q];
+                vp[k] = Vp[p0 + q];
+            }
         }
-        E[ia] = ea;
-        E[ib] = eb;
-        const int aa = relerr ? (ea > tau * fabs(va)) : 1;
-        const int ab = relerr ? (eb > tau * fabs(vb)) : 1;
-        A[ia] = (uint8_t)aa;
-        A[ib] = (uint8_t)ab;
-        lo_acc.add(va, ea, aa);
-        hi_acc.add(vb, eb, ab);
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int64_t q = c0 + threadIdx.x + (int64_t)k * LIST_THREADS;
+            if (q >= q1) break;
+            const int64_t ia = a0 + q, ib = b0 + q;
+            const double delta = fabs(va[k] + vb[k] - vp[k]) / 4.0;
+            const double S = ea[k] + eb[k];
+            double xa = ea[k], xb = eb[k];
+            if (S > 0.0) {
+                const double g = 1.0 + 2.0 * delta / S;
+                xa = xa * g + delta;
+                xb = xb * g + delta;
+            } else {
+                xa = xa + delta;
+                xb = xb + delta;
+            }
+            E[ia] = xa;
+            E[ib] = xb;
+            const int aa = relerr ? (xa > tau * fabs(va[k])) : 1;
+            const int ab = relerr ? (xb > tau * fabs(vb[k])) : 1;
+            A[ia] = (uint8_t)aa;
+            A[ib] = (uint8_t)ab;
+            lo_acc.add(va[k], xa, aa);
+            hi_acc.add(vb[k], xb, ab);
+        }
     }
     block_reduce_store(lo_acc, part, s_lo);
     block_reduce_store(hi_acc, part, s_hi);
@@ -133,10 +153,28 @@ __device__ inline void count_segment(int64_t s0, int64_t s1, int mode,
                                      SegPartials part, int64_t s) {
     Acc acc;
     acc.init();
-    for (int64_t i = s0 + threadIdx.x; i < s1; i += LIST_THREADS) {
-        const double v = V[i], e = E ? E[i] : 0.0;
-        const int a = mode == 0 ? 0 : (A_rel[i] && (mode == 1 || e > t));
-        acc.add(v, e, a);
+    // chunks of SEG regions, every load of a chunk issued before its first
+    // use (the sums keep the order of a plain strided loop)
+    constexpr int PER = SEG / LIST_THREADS;
+    for (int64_t c0 = s0; c0 < s1; c0 += SEG) {
+        double v[PER], e[PER];
+        uint8_t ar[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int64_t i = c0 + threadIdx.x + (int64_t)k * LIST_THREADS;
+            if (i < s1) {
+                v[k] = V[i];
+                e[k] = E ? E[i] : 0.0;
+                ar[k] = mode == 0 ? 0 : A_rel[i];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int64_t i = c0 + threadIdx.x + (int64_t)k * LIST_THREADS;
+            if (i >= s1) break;
+            const int a = mode == 0 ? 0 : (ar[k] && (mode == 1 || e[k] > t));
+            acc.add(v[k], e[k], a);
+        }
     }
     block_reduce_store(acc, part, s);
 }
