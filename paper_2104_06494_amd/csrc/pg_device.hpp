@@ -519,6 +519,7 @@ __device__ inline void sum_trial_parts(const double *__restrict__ src,
 // With a non-null inst_out, the children are tagged with `tag`.
 // ---------------------------------------------------------------------------
 constexpr int CS_ROUNDS = SEG / LIST_THREADS;
+static_assert(CS_ROUNDS % 2 == 0, "compaction pairs rounds");
 
 __device__ inline void compact_segment(
     int d, int64_t s0, int64_t s1, int mode, double t,
@@ -544,31 +545,60 @@ __device__ inline void compact_segment(
         if (lane == 0) wcnt[r * NW + wave] = __popcll(mask);
     }
     __syncthreads();
-    uint32_t run = 0;                       // survivors before round r
+    // destinations of the thread's survivors, round by round
+    int64_t dst[CS_ROUNDS];
+    {
+        uint32_t run = 0;                   // survivors before round r
 #pragma unroll
-    for (int r = 0; r < CS_ROUNDS; ++r) {
-        uint32_t rbase = run;
-        for (int q = 0; q < NW; ++q) {
-            if (q < wave) rbase += wcnt[r * NW + q];
-            run += wcnt[r * NW + q];
+        for (int r = 0; r < CS_ROUNDS; ++r) {
+            uint32_t rbase = run;
+            for (int q = 0; q < NW; ++q) {
+                if (q < wave) rbase += wcnt[r * NW + q];
+                run += wcnt[r * NW + q];
+            }
+            dst[r] = base + rbase + pre[r];
         }
-        if (!((act >> r) & 1u)) continue;
-        const int64_t i = s0 + r * LIST_THREADS + threadIdx.x;
-        const int64_t j = base + rbase + pre[r];
-        const int ax = K[i];
-        for (int k = 0; k < d; ++k) {
-            const double l = lo[k * ld_in + i], ww = w[k * ld_in + i];
-            const double half = ww * 0.5;
-            const bool sp = k == ax;
-            lo_out[k * ld_out + j] = l;
-            w_out[k * ld_out + j] = sp ? half : ww;
-            lo_out[k * ld_out + j + na] = sp ? l + half : l;
-            w_out[k * ld_out + j + na] = sp ? half : ww;
+    }
+    // two rounds at a time: both rounds' boxes are loaded before either is
+    // written, so a thread has two rounds of loads in flight
+#pragma unroll
+    for (int r0 = 0; r0 < CS_ROUNDS; r0 += 2) {
+        double l[2][PG_DIM_MAX], ww[2][PG_DIM_MAX], v[2];
+        int ax[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (!((act >> (r0 + h)) & 1u)) continue;
+            const int64_t i = s0 + (r0 + h) * LIST_THREADS + threadIdx.x;
+            ax[h] = K[i];
+            v[h] = V[i];
+#pragma unroll
+            for (int k = 0; k < PG_DIM_MAX; ++k) {
+                if (k < d) {
+                    l[h][k] = lo[k * ld_in + i];
+                    ww[h][k] = w[k * ld_in + i];
+                }
+            }
         }
-        Vp[j - vp_shift] = V[i];
-        if (inst_out) {
-            inst_out[j] = tag;
-            inst_out[j + na] = tag;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (!((act >> (r0 + h)) & 1u)) continue;
+            const int64_t j = dst[r0 + h];
+#pragma unroll
+            for (int k = 0; k < PG_DIM_MAX; ++k) {
+                if (k < d) {
+                    const double half = ww[h][k] * 0.5;
+                    const bool sp = k == ax[h];
+                    lo_out[k * ld_out + j] = l[h][k];
+                    w_out[k * ld_out + j] = sp ? half : ww[h][k];
+                    lo_out[k * ld_out + j + na] = sp ? l[h][k] + half : l[h][k];
+                    w_out[k * ld_out + j + na] = sp ? half : ww[h][k];
+                }
+            }
+            Vp[j - vp_shift] = v[h];
+            if (inst_out) {
+                inst_out[j] = tag;
+                inst_out[j + na] = tag;
+            }
         }
     }
 }
