@@ -331,19 +331,23 @@ __device__ inline uint64_t hist_key(double e) {
     return __builtin_bit_cast(uint64_t, e) >> HIST_SHIFT;
 }
 
-// Adds the A_rel regions of [s0, s1) to the histogram (LDS first, then one
-// atomic per non-empty bin).
+// Regions (at most) one histogram block adds up: 4 segments, so that a
+// long list needs few blocks and few global atomics.
+constexpr int64_t HIST_RANGE = 4 * SEG;
+
+// Adds the A_rel regions of [s0, s1) (at most HIST_RANGE of them) to the
+// histogram: in LDS one 64-bit atomic per region, holding the count in bits
+// 50 and up and the significand sum below (the sum of at most 2^13 32-bit
+// significands stays under 2^45, the count under 2^14), then one pair of
+// global atomics per non-empty bin.
 __device__ inline void hist_segment(int64_t s0, int64_t s1,
                                     const double *__restrict__ E,
                                     const uint8_t *__restrict__ A_rel,
                                     uint64_t kmax, uint32_t *__restrict__ gcnt,
                                     unsigned long long *__restrict__ gsum) {
-    __shared__ uint32_t lc[HIST_BINS];
-    __shared__ unsigned long long ls[HIST_BINS];
-    for (int b = threadIdx.x; b < HIST_BINS; b += blockDim.x) {
-        lc[b] = 0;
-        ls[b] = 0;
-    }
+    constexpr unsigned long long ONE = 1ull << 50;
+    __shared__ unsigned long long lcs[HIST_BINS];
+    for (int b = threadIdx.x; b < HIST_BINS; b += blockDim.x) lcs[b] = 0;
     __syncthreads();
     for (int64_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
         if (!A_rel[i]) continue;
@@ -351,19 +355,21 @@ __device__ inline void hist_segment(int64_t s0, int64_t s1,
         const uint64_t key = bits >> HIST_SHIFT;
         uint64_t j = key >= kmax ? 0 : kmax - key;
         if (j > HIST_BINS - 1) j = HIST_BINS - 1;
-        atomicAdd(&lc[j], 1u);
+        unsigned long long add = ONE;
         if (j < HIST_BINS - 1) {
             const uint64_t ef = (bits >> 52) & 0x7ff;
             uint64_t m = bits & ((1ull << 52) - 1);
             if (ef) m |= 1ull << 52;
-            atomicAdd(&ls[j], (unsigned long long)(m >> HIST_DROP));
+            add += (unsigned long long)(m >> HIST_DROP);
         }
+        atomicAdd(&lcs[j], add);
     }
     __syncthreads();
     for (int b = threadIdx.x; b < HIST_BINS; b += blockDim.x) {
-        if (lc[b]) {
-            atomicAdd(&gcnt[b], lc[b]);
-            atomicAdd(&gsum[b], ls[b]);
+        const unsigned long long v = lcs[b];
+        if (v) {
+            atomicAdd(&gcnt[b], (uint32_t)(v >> 50));
+            atomicAdd(&gsum[b], v & (ONE - 1));
         }
     }
 }

@@ -81,14 +81,27 @@ __global__ void k_search_init(SearchState *__restrict__ S, int64_t n,
     *S = s;
 }
 
+// Regions per histogram block for a list of more than 256 segments: about
+// n / 256, rounded up to whole segments, at most HIST_RANGE.
+__host__ __device__ inline int64_t hist_span(int64_t n) {
+    const int64_t nseg = (n + SEG - 1) / SEG;
+    int64_t per = (nseg + 255) / 256;
+    if (per > HIST_RANGE / SEG) per = HIST_RANGE / SEG;
+    return per * SEG;
+}
+
 // Error histogram of the A_rel regions, one block per segment, then the
 // trials it decides (see hist_walk).
 __global__ void __launch_bounds__(LIST_THREADS)
 k_hist(int64_t n, const double *__restrict__ E,
        const uint8_t *__restrict__ A_rel, const SearchState *__restrict__ S,
        uint32_t *__restrict__ cnt, unsigned long long *__restrict__ sum) {
-    const int64_t s0 = (int64_t)blockIdx.x * SEG;
-    const int64_t s1 = s0 + SEG < n ? s0 + SEG : n;
+    // lists of up to 256 segments: one block each; longer ones: blocks of
+    // up to HIST_RANGE regions, about 256 of them
+    const int64_t nseg = (n + SEG - 1) / SEG;
+    const int64_t span = nseg <= 256 ? SEG : hist_span(n);
+    const int64_t s0 = (int64_t)blockIdx.x * span;
+    const int64_t s1 = s0 + span < n ? s0 + span : n;
     hist_segment(s0, s1, E, A_rel, hist_key(S->mx), cnt, sum);
 }
 
@@ -282,7 +295,9 @@ hipError_t launch_search_hist(hipStream_t st, int64_t n, const double *E,
                               const uint8_t *A_rel, SearchState *S,
                               uint32_t *cnt, unsigned long long *sum) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_hist, dim3((unsigned)seg_count(n, 0)),
+    const int64_t nseg = seg_count(n, 0);
+    const int64_t span = nseg <= 256 ? SEG : hist_span(n);
+    hipLaunchKernelGGL(k_hist, dim3((unsigned)((n + span - 1) / span)),
                        dim3(LIST_THREADS), 0, st, n, E, A_rel, S, cnt, sum);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
