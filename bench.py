@@ -424,9 +424,9 @@ def main():
                          "reserves 2^21 regions of workspace)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not "
-              "supported (the method's multi-GPU sharding is a design note, not code)",
-              file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not "
+              "supported (how the method would shard over several GPUs is described "
+              "in the design notes, not implemented)", file=sys.stderr)
         sys.exit(2)
     {"headline": headline, "batched": batched_mode, "adjoint": adjoint_mode,
      "suite": suite_mode, "errors": errors_mode, "integrand": integrand_mode,
