@@ -263,7 +263,8 @@ def suite_mode(args):
     (1e-3 down to 1.024e-10, a fifth at a time), each integrand until its
     first run that does not converge, as the paper reports it; then the
     filtering ablation (threshold search off) on the same sweep for the
-    5-d f4. One JSON line per run. Context of 2^26 regions (20 GB at d=8)."""
+    5-d f4. One JSON line per run. Context of --suite-capacity regions
+    (default 2^28, 80 GB at d=8)."""
     import torch
     import paper_2104_06494_amd as pg
     import workloads as W
@@ -411,8 +412,9 @@ def main():
                     help="batched run without the single-run comparison")
     ap.add_argument("--batch-count", type=int, default=0,
                     help="first integrals of the batch only (0 = all 1024)")
-    ap.add_argument("--suite-capacity", type=int, default=1 << 26,
-                    help="regions of the context the suite sweep runs in")
+    ap.add_argument("--suite-capacity", type=int, default=1 << 28,
+                    help="regions of the context the suite sweep runs in "
+                         "(2^28: 80 GB at d=8)")
     ap.add_argument("--suite-only", default="",
                     help="suite integrands whose name starts with this only")
     ap.add_argument("--error-rule", default="raw", choices=["raw", "null4"],
