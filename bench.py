@@ -40,8 +40,9 @@ F_GAUSSIAN_D5 = 47.0
 # HBM bytes per evaluate launch of this workload from FETCH_SIZE / WRITE_SIZE
 # (scaled by a plain copy), valid only for the kernel source they were taken
 # on (first 16 hex digits of the sha256 of pg_eval_kernels.hpp followed by
-# pg_eval_defs.hpp); reported as null otherwise.
-EVAL_TRAFFIC = {"bytes_per_launch": 37762550.9, "kernel_sha256": "fefbfb583f0bad4d",
+# pg_eval_defs.hpp, comments and blank space removed); reported as null
+# otherwise.
+EVAL_TRAFFIC = {"bytes_per_launch": 37762550.9, "kernel_sha256": "430586abe27e8bd5",
                 "profile": "profiles/evaluate_gaussian_d5_counters.txt"}
 # MI355X FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz.
 PEAK_FP64_TFLOPS = 78.6
@@ -49,11 +50,16 @@ PEAK_FP64_TFLOPS = 78.6
 
 def _kernel_sha():
     """sha256 (16 hex digits) of the evaluate kernel's source: its header and
-    the definitions it is built from (rule, parameters, exponential)."""
+    the definitions it is built from (rule, parameters, exponential), with
+    comments and blank space removed, so that only code changes count."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in ("pg_eval_kernels.hpp", "pg_eval_defs.hpp"):
-        h.update(open(os.path.join(ROOT, "paper_2104_06494_amd", "csrc", name), "rb").read())
+        src = open(os.path.join(ROOT, "paper_2104_06494_amd", "csrc", name)).read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

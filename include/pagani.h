@@ -22,6 +22,7 @@
  *      PG_PRODUCT_PEAK  prod_k 1 / (a_k^-2 + (x_k - u_k)^2)  params a[d], u[d]
  *                       (a_k != 0)
  *      PG_GAUSSIAN      exp(-sum_k a_k^2 (x_k - u_k)^2)      params a[d], u[d]
+ *                       (|a_k| up to about 3e4 on boxes of unit size)
  *      PG_OSCILLATORY   cos(2 pi u_1 + sum_k a_k x_k)        params a[d], u_1
  *      PG_CORNER_PEAK   (1 + sum_k a_k x_k)^-(d+1)          params a[d]
  *                       (1 + sum_k a_k x_k > 0 on the box)

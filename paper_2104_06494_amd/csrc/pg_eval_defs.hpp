@@ -22,8 +22,9 @@ constexpr int EVAL_MAX_WAVES = 8;
 // the polynomial's relative error is 1.7e-17), Horner's rule; then 2^n by
 // ldexp, which underflows gradually and reaches 0 below -745 without a
 // test. Largest error 0.91 ulp on 2e5 points of [-745, 0] against a
-// 40-digit reference. NaN in, NaN out; x = -inf (an exponent that
-// overflowed) gives NaN.
+// 40-digit reference. Domain: -1.4e9 < x <= 0 (below, n leaves int's range;
+// the Gaussian's exponent stays in it unless some a_k^2 exceeds 1e9).
+// NaN in, NaN out.
 __device__ __forceinline__ double exp_nonpos(double x) {
     constexpr double LOG2E = 1.4426950408889634;      // RN(1 / ln 2)
     constexpr double LN2_HI = 0.6931471805599453;     // RN(ln 2)
