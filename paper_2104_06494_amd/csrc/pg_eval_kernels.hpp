@@ -203,15 +203,45 @@ k_evaluate(const FParams P, const Rule R, int64_t n,
         int u0 = D + NPAIR;
         int m = wave - (u0 % W);
         if (m < 0) m += W;
-        for (; m < N5; m += W) {
-            double x[D];
+        if constexpr (FAM == PG_GAUSSIAN) {
+            // The Gaussian's exponent at the vertex c + sigma l5 (sigma_k =
+            // +-1) expands as S0 + sum_k sigma_k B_k with p = c - u,
+            // S0 = sum a_k^2 (p_k^2 + l5_k^2) and B_k = 2 a_k^2 p_k l5_k, so
+            // a unit of four vertices costs D - 2 FMAs for the sign choices
+            // they share and two additions each, instead of rebuilding every
+            // point. The terms are of the order of the region's spread of
+            // the exponent, so their rounding stays far inside the
+            // tolerance of the point-by-point sum.
+            double S0 = 0.0, B[D];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int b = 4 * m + q;
+            for (int k = 0; k < D; ++k) {
+                const double pk = c[k] - PP.p[D + k];
+                S0 = fma(PP.p[k], fma(pk, pk, l5[k] * l5[k]), S0);
+                B[k] = (2.0 * PP.p[k] * pk) * l5[k];
+            }
+            for (; m < N5; m += W) {
+                double base = S0;
 #pragma unroll
-                for (int k = 0; k < D; ++k)
-                    x[k] = fma(((b >> k) & 1) ? -1.0 : 1.0, l5[k], c[k]);
-                S5 += integrand<FAM, D>(x, PP);
+                for (int k = 2; k < D; ++k)
+                    base = fma((((4 * m) >> k) & 1) ? -1.0 : 1.0, B[k], base);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double s0 = (q & 1) ? base - B[0] : base + B[0];
+                    const double sv = (q & 2) ? s0 - B[1] : s0 + B[1];
+                    S5 += exp_nonpos(-sv);
+                }
+            }
+        } else {
+            for (; m < N5; m += W) {
+                double x[D];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int b = 4 * m + q;
+#pragma unroll
+                    for (int k = 0; k < D; ++k)
+                        x[k] = fma(((b >> k) & 1) ? -1.0 : 1.0, l5[k], c[k]);
+                    S5 += integrand<FAM, D>(x, PP);
+                }
             }
         }
     }
