@@ -42,7 +42,7 @@ F_GAUSSIAN_D5 = 47.0
 # on (first 16 hex digits of the sha256 of pg_eval_kernels.hpp followed by
 # pg_eval_defs.hpp, comments and blank space removed); reported as null
 # otherwise.
-EVAL_TRAFFIC = {"bytes_per_launch": 37762550.9, "kernel_sha256": "430586abe27e8bd5",
+EVAL_TRAFFIC = {"bytes_per_launch": 37759311.2, "kernel_sha256": "ca1f2b37fe775935",
                 "profile": "profiles/evaluate_gaussian_d5_counters.txt"}
 # MI355X FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz.
 PEAK_FP64_TFLOPS = 78.6
