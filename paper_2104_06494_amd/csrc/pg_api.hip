@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -43,6 +44,11 @@ struct pg_context {
     // there directly, so no copy is queued before a wait
     Totals *htot_dev = nullptr;
     SearchState *hstate_dev = nullptr;
+    // sequence word written after them (mapped as well), and the last value
+    // the host asked for: the host polls it instead of waiting for the
+    // stream, so it sees the values as soon as they land
+    uint64_t *hseq = nullptr, *hseq_dev = nullptr;
+    uint64_t seq = 0;
     // many-integral runs
     uint32_t *inst[2] = {nullptr, nullptr};
     BInst *b_inst = nullptr, *hb_inst = nullptr;
@@ -406,11 +412,38 @@ int sync_tot(pg_context *ctx, Totals *out) {
     return PG_OK;
 }
 
-// The totals a reduce launched with host_tot = ctx->htot_dev left in the
-// mapped host copy: wait for the stream (the kernel's writes to host memory
-// are visible once it has completed), then read them.
-int wait_tot(pg_context *ctx, Totals *out) {
-    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream));
+// Sequence number for the next reduce that publishes to the host.
+uint64_t next_seq(pg_context *ctx) { return ++ctx->seq; }
+
+// Wait until the reduce tagged `seq` has published its values to the mapped
+// host copies: spin on the sequence word; every 1024 polls ask the stream
+// whether it has stopped (then the word must be there, else the kernel
+// failed) or has failed.
+int wait_seq(pg_context *ctx, uint64_t seq) {
+    const volatile uint64_t *word = ctx->hseq;
+    for (uint32_t k = 1;; ++k) {
+        if (*word == seq) break;
+        if ((k & 1023) == 0) {
+            const hipError_t e = hipStreamQuery(ctx->stream);
+            if (e == hipSuccess) {
+                if (*word == seq) break;
+                return fail(ctx, PG_EHIP, "stream idle before the totals "
+                            "of reduce %llu arrived", (unsigned long long)seq);
+            }
+            if (e != hipErrorNotReady)
+                return fail(ctx, PG_EHIP, "stream failed: %s",
+                            hipGetErrorString(e));
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    return PG_OK;
+}
+
+// The totals of the reduce tagged `seq` (launched with host_tot =
+// ctx->htot_dev and host_seq = ctx->hseq_dev).
+int wait_tot(pg_context *ctx, uint64_t seq, Totals *out) {
+    int rc = wait_seq(ctx, seq);
+    if (rc) return rc;
     *out = *ctx->htot;
     return PG_OK;
 }
@@ -464,16 +497,20 @@ int search(pg_context *ctx, int64_t n, const double *E, const uint8_t *A_rel,
                                               count->V, E, A_rel, ctx->dstate,
                                               ctx->part));
             // the totals and the search state go straight to the host
+            const uint64_t sq = next_seq(ctx);
             HIP_OR_FAIL(ctx, launch_reduce_scan(st, seg_count(n, count->paired),
                                                 ctx->part, ctx->off,
                                                 ctx->dtot, ctx->htot_dev,
-                                                ctx->dstate, ctx->hstate_dev));
+                                                ctx->dstate, ctx->hstate_dev,
+                                                ctx->hseq_dev, sq));
+            const int rc = wait_seq(ctx, sq);
+            if (rc) return rc;
         } else {
             HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->hstate, ctx->dstate,
                                             sizeof(SearchState),
                                             hipMemcpyDeviceToHost, st));
+            HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
         }
-        HIP_OR_FAIL(ctx, hipStreamSynchronize(st));
         if (ctx->hstate->done) break;
     }
     const SearchState &S = *ctx->hstate;
@@ -558,6 +595,11 @@ int pg_context_create(int device, int dim_max, int64_t capacity,
             hipSuccess ||
         hipHostGetDevicePointer((void **)&ctx->hstate_dev, ctx->hstate, 0) !=
             hipSuccess ||
+        hipHostMalloc((void **)&ctx->hseq, 64,
+                      hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostGetDevicePointer((void **)&ctx->hseq_dev, ctx->hseq, 0) !=
+            hipSuccess ||
         hipHostMalloc((void **)&ctx->hb_inst,
                       sizeof(BInst) * INST_STAGES * BATCH_MAX_SLOTS,
                       0) != hipSuccess ||
@@ -582,6 +624,7 @@ int pg_context_create(int device, int dim_max, int64_t capacity,
         pg_context_destroy(ctx);
         return PG_ENOMEM;
     }
+    *ctx->hseq = 0;
     char *b = (char *)ctx->ws;
     for (int q = 0; q < 2; ++q) {
         ctx->lo[q] = (double *)(b + L.lo[q]);
@@ -636,6 +679,7 @@ void pg_context_destroy(pg_context *ctx) {
     for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
     if (ctx->htot) (void)hipHostFree(ctx->htot);
     if (ctx->hstate) (void)hipHostFree(ctx->hstate);
+    if (ctx->hseq) (void)hipHostFree(ctx->hseq);
     void *pinned[] = {ctx->hb_inst, ctx->hb_state, ctx->hb_tot, ctx->hb_table,
                       ctx->hb_order, ctx->hb_new, ctx->hb_gtable, ctx->hb_git};
     for (void *q : pinned)
@@ -859,14 +903,18 @@ int pg_integrate(pg_context *ctx, const pg_integrand *f, const double *lo,
         std::fwrite(hd, 4, 2, tr);
         std::fwrite(zero, 8, 2, tr);
     }
-    // timing events: 5 per iteration (level 1 records only the two around
-    // EVALUATE, level 2 all five)
+    // timing events: 5 per iteration (level 1: the EVALUATE dispatch's own
+    // start and end; level 2 also markers after the later phases)
     const int timing = o.timing < 0 ? 0 : o.timing;
     if (timing) {
         const size_t need = 5 * (size_t)o.max_iters;
         while (ctx->events.size() < need) {
             hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) {
+            // timing only: no system-scope fence (and so no cache write-back)
+            // when an event is recorded; the times are read after the
+            // run's final stream synchronisation
+            if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) !=
+                hipSuccess) {
                 if (tr) std::fclose(tr);
                 return fail(ctx, PG_EHIP, "hipEventCreate failed");
             }
@@ -908,21 +956,23 @@ int pg_integrate(pg_context *ctx, const pg_integrand *f, const double *lo,
     for (it = 1; it <= o.max_iters; ++it) {
         const int paired = it > 1;
         hipEvent_t *ev = timing ? &ctx->events[5 * (it - 1)] : nullptr;
-        if (timing) RUN_FAIL(hipEventRecord(ev[0], st));
         RUN_FAIL(launch_evaluate(st, f->family, d, P, R, n, ctx->lo[cur],
                                  ctx->w[cur], ld, ctx->V, ctx->E, ctx->K,
-                                 eval_waves(d, n)));
+                                 eval_waves(d, n), nullptr, nullptr,
+                                 timing ? ev[0] : nullptr,
+                                 timing ? ev[1] : nullptr));
         ++nev;
-        if (timing) RUN_FAIL(hipEventRecord(ev[1], st));
         res.regions_evaluated += n;
         RUN_FAIL(launch_classify(st, n, paired, ctx->V, ctx->E, ctx->Vp, tau,
                                  o.relerr_filter, ctx->A, ctx->part));
         const int64_t nseg = seg_count(n, paired);
+        const uint64_t sq = next_seq(ctx);
         RUN_FAIL(launch_reduce_scan(st, nseg, ctx->part, ctx->off, ctx->dtot,
-                                    ctx->htot_dev));
+                                    ctx->htot_dev, nullptr, nullptr,
+                                    ctx->hseq_dev, sq));
         if (timing > 1) RUN_FAIL(hipEventRecord(ev[2], st));
         Totals T;
-        RUN_RC(wait_tot(ctx, &T));
+        RUN_RC(wait_tot(ctx, sq, &T));
         const double v = T.v, e = T.e;
         v_tot = v + v_f;
         e_tot = e + e_f;

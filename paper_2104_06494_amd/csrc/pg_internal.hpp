@@ -211,7 +211,9 @@ hipError_t launch_evaluate(hipStream_t st, int family, int d,
                            const double *lo, const double *w, int64_t ld,
                            double *V, double *E, uint8_t *K, int waves,
                            const uint32_t *inst = nullptr,
-                           const FParams *table = nullptr);
+                           const FParams *table = nullptr,
+                           hipEvent_t t_start = nullptr,
+                           hipEvent_t t_stop = nullptr);
 bool evaluate_supported(int family, int d);
 hipError_t launch_fvalues(hipStream_t st, int family, int d, const FParams &P,
                           int64_t n, const double *x, int64_t ld, double *y);
@@ -226,12 +228,15 @@ hipError_t launch_seg_count(hipStream_t st, int64_t n, int paired, double t,
                             const uint8_t *A_rel, const SearchState *S,
                             SegPartials part);
 // host_tot / host_state (device addresses of mapped pinned host memory, or
-// NULL): the kernel also leaves there the totals and a copy of *state.
+// NULL): the kernel also leaves there the totals and a copy of *state, and
+// then writes `seq` to host_seq (also mapped, or NULL) once both are
+// visible to the host.
 hipError_t launch_reduce_scan(hipStream_t st, int64_t nseg, SegPartials part,
                               uint32_t *offsets, Totals *tot,
                               Totals *host_tot = nullptr,
                               const SearchState *state = nullptr,
-                              SearchState *host_state = nullptr);
+                              SearchState *host_state = nullptr,
+                              uint64_t *host_seq = nullptr, uint64_t seq = 0);
 hipError_t launch_search_init(hipStream_t st, SearchState *S, int64_t n,
                               double e_it, double allowance, int mem,
                               const Totals *minmax);

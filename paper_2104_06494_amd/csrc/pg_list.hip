@@ -54,13 +54,21 @@ __global__ void __launch_bounds__(SCAN_THREADS)
 k_reduce_scan(int64_t nseg, SegPartials part, uint32_t *__restrict__ offsets,
               Totals *__restrict__ tot, Totals *__restrict__ host_tot,
               const SearchState *__restrict__ state,
-              SearchState *__restrict__ host_state) {
+              SearchState *__restrict__ host_state, uint64_t *host_seq,
+              uint64_t seq) {
     reduce_scan_segments(0, nseg, part, offsets, tot);
     // the host's copies (pinned host memory mapped into the device's
     // address space), so that no copy has to be queued behind this kernel
     if (threadIdx.x == 0) {
         if (host_tot) *host_tot = *tot;
         if (host_state) *host_state = *state;
+        // then the sequence number the host polls for: once it reads `seq`
+        // there, the copies above are visible to it as well
+        if (host_seq) {
+            __threadfence_system();
+            __hip_atomic_store(host_seq, seq, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
+        }
     }
 }
 
@@ -277,9 +285,11 @@ hipError_t launch_seg_count(hipStream_t st, int64_t n, int paired, double t,
 hipError_t launch_reduce_scan(hipStream_t st, int64_t nseg, SegPartials part,
                               uint32_t *offsets, Totals *tot, Totals *host_tot,
                               const SearchState *state,
-                              SearchState *host_state) {
+                              SearchState *host_state, uint64_t *host_seq,
+                              uint64_t seq) {
     hipLaunchKernelGGL(k_reduce_scan, dim3(1), dim3(SCAN_THREADS), 0, st, nseg,
-                       part, offsets, tot, host_tot, state, host_state);
+                       part, offsets, tot, host_tot, state, host_state,
+                       host_seq, seq);
     return hipGetLastError();
 }
 
