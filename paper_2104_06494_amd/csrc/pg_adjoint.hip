@@ -176,7 +176,7 @@ k_batch_adjoint(const BSeg *__restrict__ segs, const BInst *__restrict__ inst,
                 const uint32_t *__restrict__ offsets, LeafOut out) {
     constexpr int NP = n_grad<FAM, D>();
     constexpr int NW = LIST_THREADS / 64;
-    __shared__ uint16_t idx[SEG];
+    __shared__ uint16_t idx[BSEG];
     __shared__ uint32_t wtot[NW];
     __shared__ double red[NW][NP];
     const int64_t s = blockIdx.x / ADJ_SPLIT;

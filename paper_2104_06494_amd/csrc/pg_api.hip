@@ -114,7 +114,8 @@ Layout layout(int dim_max, int64_t cap) {
     L.K = bump(at, cap);
     L.A = bump(at, cap);
     L.A2 = bump(at, cap);
-    // segments: single list <= 2 ceil(cap / SEG) + 2; many integrals add at
+    // segments: single list <= 2 ceil(cap / SEG) + 2 (the many-integral
+    // list's BSEG-long segments number fewer); many integrals add at
     // most two partial segments per slot
     L.nseg = 2 * ((cap + SEG - 1) / SEG) + 2 * BATCH_MAX_SLOTS + 2;
     L.pv = bump(at, sizeof(double) * L.nseg);
@@ -1297,11 +1298,11 @@ static int run_batch(pg_context *ctx, int family, int dim, int B,
             I.seg0 = seg0;
             I.cls0 = cls0;
             if (S.paired) {
-                const int64_t nh = (S.n / 2 + SEG - 1) / SEG;
+                const int64_t nh = (S.n / 2 + BSEG - 1) / BSEG;
                 I.nseg = 2 * nh;
                 I.ncls = nh;
             } else {
-                I.nseg = (S.n + SEG - 1) / SEG;
+                I.nseg = (S.n + BSEG - 1) / BSEG;
                 I.ncls = I.nseg;
             }
             seg0 += I.nseg;

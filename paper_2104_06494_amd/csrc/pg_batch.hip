@@ -22,17 +22,17 @@ __global__ void k_batch_tables(int nslots, const int32_t *__restrict__ order,
     const BInst I = inst[slot];
     if (!I.paired) {
         for (int64_t j = 0; j < I.nseg; ++j) {
-            const int64_t s0 = I.start + j * SEG;
-            const int64_t s1 = s0 + SEG < I.start + I.n ? s0 + SEG : I.start + I.n;
+            const int64_t s0 = I.start + j * BSEG;
+            const int64_t s1 = s0 + BSEG < I.start + I.n ? s0 + BSEG : I.start + I.n;
             segs[I.seg0 + j] = BSeg{s0, s1, slot, 0};
             cls[I.cls0 + j] = BCls{s0, s1, I.seg0 + j, -1, slot, 0};
         }
         return;
     }
     const int64_t half = I.n / 2;
-    const int64_t nh = (half + SEG - 1) / SEG;
+    const int64_t nh = (half + BSEG - 1) / BSEG;
     for (int64_t j = 0; j < nh; ++j) {
-        const int64_t q0 = j * SEG, q1 = q0 + SEG < half ? q0 + SEG : half;
+        const int64_t q0 = j * BSEG, q1 = q0 + BSEG < half ? q0 + BSEG : half;
         segs[I.seg0 + j] = BSeg{I.start + q0, I.start + q1, slot, 0};
         segs[I.seg0 + nh + j] = BSeg{I.start + half + q0, I.start + half + q1,
                                      slot, 1};
@@ -202,7 +202,7 @@ k_batch_compact(int d, const BSeg *__restrict__ segs,
     const BInst &I = inst[sg.slot];
     const int mode = batch_mode(I, states[sg.slot]);
     if (mode == 0) return;
-    compact_segment(d, sg.start, sg.end, mode, states[sg.slot].t_acc, A_rel, E,
+    compact_segment<BSEG>(d, sg.start, sg.end, mode, states[sg.slot].t_acc, A_rel, E,
                     V, K, lo, w, ld, I.out_start + offsets[blockIdx.x], I.na,
                     lo_out, w_out, ld, Vp, I.out_start - I.out_start / 2,
                     inst_out, sg.slot);

@@ -331,9 +331,13 @@ __device__ inline uint64_t hist_key(double e) {
     return __builtin_bit_cast(uint64_t, e) >> HIST_SHIFT;
 }
 
-// Regions (at most) one histogram block adds up: 4 segments, so that a
-// long list needs few blocks and few global atomics.
-constexpr int64_t HIST_RANGE = 4 * SEG;
+// Regions (at most) one histogram block adds up: whole segments, as many
+// as the packed LDS word allows, so that a long list needs few blocks and
+// few global atomics.
+constexpr int64_t HIST_RANGE = 8192;
+static_assert(HIST_RANGE % SEG == 0 && HIST_RANGE >= BSEG &&
+                  HIST_RANGE <= (1 << 13),
+              "histogram block range");
 
 // Adds the A_rel regions of [s0, s1) (at most HIST_RANGE of them) to the
 // histogram: in LDS one 64-bit atomic per region, holding the count in bits
@@ -516,17 +520,16 @@ __device__ inline void sum_trial_parts(const double *__restrict__ src,
 }
 
 // ---------------------------------------------------------------------------
-// FILTER + parent update + SPLIT of one segment [s0, s1) by one block: the
-// flags of all SEG / LIST_THREADS rounds are read first (region
+// FILTER + parent update + SPLIT of one segment [s0, s1) of at most SEGLEN
+// regions by one block: the flags of all SEGLEN / LIST_THREADS rounds are
+// read first (region
 // s0 + r * LIST_THREADS + tid in round r, coalesced), their wave ballots give
 // the prefix in (round, wave) order after one barrier, and the survivors are
 // then copied and bisected: the survivor at output index j = base + prefix
 // goes to j (lower half) and j + na (upper half), with Vp[j - vp_shift] = V.
 // With a non-null inst_out, the children are tagged with `tag`.
 // ---------------------------------------------------------------------------
-constexpr int CS_ROUNDS = SEG / LIST_THREADS;
-static_assert(CS_ROUNDS % 2 == 0, "compaction pairs rounds");
-
+template <int SEGLEN>
 __device__ inline void compact_segment(
     int d, int64_t s0, int64_t s1, int mode, double t,
     const uint8_t *__restrict__ A_rel, const double *__restrict__ E,
@@ -535,6 +538,8 @@ __device__ inline void compact_segment(
     int64_t ld_in, int64_t base, int64_t na, double *__restrict__ lo_out,
     double *__restrict__ w_out, int64_t ld_out, double *__restrict__ Vp,
     int64_t vp_shift, uint32_t *__restrict__ inst_out, uint32_t tag) {
+    constexpr int CS_ROUNDS = SEGLEN / LIST_THREADS;
+    static_assert(CS_ROUNDS % 2 == 0, "compaction pairs rounds");
     constexpr int NW = LIST_THREADS / 64;
     __shared__ uint32_t wcnt[CS_ROUNDS * NW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;

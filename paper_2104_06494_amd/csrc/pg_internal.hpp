@@ -13,8 +13,14 @@ namespace pg {
 // Regions handled by one block of the list kernels (classify, threshold
 // count, compact + split). A segment is a contiguous run of at most SEG
 // regions; segments never straddle the two halves of a paired list.
-constexpr int SEG = 2048;
+constexpr int SEG = 1024;
 constexpr int LIST_THREADS = 256;
+// Segment length of the many-integral list (pg_batch.hip, pg_adjoint.hip):
+// the derivative kernel gathers each segment's leaves into one block, which
+// wants long segments, while the single list gains from more, shorter
+// blocks on its mid-sized lists.
+constexpr int BSEG = 2048;
+static_assert(SEG <= BSEG && BSEG % SEG == 0, "segment lengths");
 // Blocks (at most) and threads per block of a threshold-trial pass.
 constexpr int TRIAL_BLOCKS = 256;
 constexpr int TRIAL_THREADS = 1024;

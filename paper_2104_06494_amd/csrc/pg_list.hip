@@ -204,7 +204,7 @@ k_compact_split(int d, int64_t n, int paired, double t,
                 double *__restrict__ Vp) {
     int64_t s0, s1;
     seg_range(blockIdx.x, n, paired, &s0, &s1);
-    compact_segment(d, s0, s1, E ? 2 : 1, t, A_rel, E, V, K, lo, w, ld_in,
+    compact_segment<SEG>(d, s0, s1, E ? 2 : 1, t, A_rel, E, V, K, lo, w, ld_in,
                     offsets[blockIdx.x], na, lo_out, w_out, ld_out, Vp, 0,
                     nullptr, 0);
 }
