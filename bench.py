@@ -80,8 +80,8 @@ def headline(args):
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ts = time.perf_counter()
-        # HIP events on the EVALUATE dispatches only (the roofline's
-        # duration); a full phase breakdown would add 3 markers an iteration
+        # HIP events around the EVALUATE launches only (the roofline's
+        # duration); a full phase breakdown would add 3 events an iteration
         r = ctx.integrate_workload(wl, timing=1)
         step_s.append(time.perf_counter() - ts)
         results.append(r)

@@ -113,12 +113,10 @@ typedef struct {
                                  0: off, for sign-changing integrands (3.5.1) */
     int threshold_filter;     /* 1: threshold search on (Algorithm 3); 0: off */
     int64_t max_regions;      /* cap on the live list; 0: context capacity */
-    int timing;               /* HIP events on the stream: 1: each
-                                 EVALUATE launch takes the dispatch's own
-                                 start and end times (phase_ms[0] only, no
-                                 marker queued); 2: also a marker after each
-                                 later phase; 0: none. Each event costs
-                                 the run a little time. */
+    int timing;               /* HIP events on the stream: 1 around each
+                                 EVALUATE launch (phase_ms[0] only), 2
+                                 around every phase; 0: none. Each event
+                                 costs the run a few microseconds. */
     const char *trace_path;   /* non-NULL: write the decision trace (below) */
     int error_rule;           /* pg_error_rule */
 } pg_options;

@@ -904,8 +904,8 @@ int pg_integrate(pg_context *ctx, const pg_integrand *f, const double *lo,
         std::fwrite(hd, 4, 2, tr);
         std::fwrite(zero, 8, 2, tr);
     }
-    // timing events: 5 per iteration (level 1: the EVALUATE dispatch's own
-    // start and end; level 2 also markers after the later phases)
+    // timing events: 5 per iteration (level 1 records only the two around
+    // EVALUATE, level 2 all five)
     const int timing = o.timing < 0 ? 0 : o.timing;
     if (timing) {
         const size_t need = 5 * (size_t)o.max_iters;
@@ -957,12 +957,12 @@ int pg_integrate(pg_context *ctx, const pg_integrand *f, const double *lo,
     for (it = 1; it <= o.max_iters; ++it) {
         const int paired = it > 1;
         hipEvent_t *ev = timing ? &ctx->events[5 * (it - 1)] : nullptr;
+        if (timing) RUN_FAIL(hipEventRecord(ev[0], st));
         RUN_FAIL(launch_evaluate(st, f->family, d, P, R, n, ctx->lo[cur],
                                  ctx->w[cur], ld, ctx->V, ctx->E, ctx->K,
-                                 eval_waves(d, n), nullptr, nullptr,
-                                 timing ? ev[0] : nullptr,
-                                 timing ? ev[1] : nullptr));
+                                 eval_waves(d, n)));
         ++nev;
+        if (timing) RUN_FAIL(hipEventRecord(ev[1], st));
         res.regions_evaluated += n;
         RUN_FAIL(launch_classify(st, n, paired, ctx->V, ctx->E, ctx->Vp, tau,
                                  o.relerr_filter, ctx->A, ctx->part));

@@ -2,7 +2,6 @@
 // instantiated per family in pg_eval_family.hip).
 #include "pg_internal.hpp"
 
-#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 namespace pg {
@@ -72,23 +71,14 @@ hipError_t launch_evaluate(hipStream_t st, int family, int d,
                            const FParams &P, const Rule &R, int64_t n,
                            const double *lo, const double *w, int64_t ld,
                            double *V, double *E, uint8_t *K, int waves,
-                           const uint32_t *inst, const FParams *table,
-                           hipEvent_t t_start, hipEvent_t t_stop) {
+                           const uint32_t *inst, const FParams *table) {
     EvalKernel k = eval_kernel(family, d, inst != nullptr);
     if (!k) return hipErrorInvalidValue;
     if (n <= 0) return hipSuccess;
     const int64_t blocks = (n + 63) / 64;
     const size_t lds = sizeof(double) * 64 * (size_t)(d + (waves > 1 ? 5 * waves : 0));
-    if (t_start || t_stop) {
-        // the events take the dispatch's own start and end times: no marker
-        // is queued around the kernel
-        hipExtLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * waves),
-                              (uint32_t)lds, st, t_start, t_stop, 0u, P, R, n,
-                              lo, w, ld, V, E, K, inst, table);
-    } else {
-        hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * waves), lds,
-                           st, P, R, n, lo, w, ld, V, E, K, inst, table);
-    }
+    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * waves), lds, st, P,
+                       R, n, lo, w, ld, V, E, K, inst, table);
     return hipGetLastError();
 }
 

@@ -217,9 +217,7 @@ hipError_t launch_evaluate(hipStream_t st, int family, int d,
                            const double *lo, const double *w, int64_t ld,
                            double *V, double *E, uint8_t *K, int waves,
                            const uint32_t *inst = nullptr,
-                           const FParams *table = nullptr,
-                           hipEvent_t t_start = nullptr,
-                           hipEvent_t t_stop = nullptr);
+                           const FParams *table = nullptr);
 bool evaluate_supported(int family, int d);
 hipError_t launch_fvalues(hipStream_t st, int family, int d, const FParams &P,
                           int64_t n, const double *x, int64_t ld, double *y);
