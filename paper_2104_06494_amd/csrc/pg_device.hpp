@@ -326,6 +326,7 @@ constexpr int HIST_MBITS = 5;
 constexpr int HIST_SHIFT = 52 - HIST_MBITS;
 constexpr int HIST_DROP = 21;                  // 32 of 53 significand bits kept
 constexpr int HIST_THREADS = 1024;
+constexpr int HIST_UNROLL = 8;        // regions a thread loads at once
 
 __device__ inline uint64_t hist_key(double e) {
     return __builtin_bit_cast(uint64_t, e) >> HIST_SHIFT;
@@ -353,20 +354,34 @@ __device__ inline void hist_segment(int64_t s0, int64_t s1,
     __shared__ unsigned long long lcs[HIST_BINS];
     for (int b = threadIdx.x; b < HIST_BINS; b += blockDim.x) lcs[b] = 0;
     __syncthreads();
-    for (int64_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
-        if (!A_rel[i]) continue;
-        const uint64_t bits = __builtin_bit_cast(uint64_t, E[i]);
-        const uint64_t key = bits >> HIST_SHIFT;
-        uint64_t j = key >= kmax ? 0 : kmax - key;
-        if (j > HIST_BINS - 1) j = HIST_BINS - 1;
-        unsigned long long add = ONE;
-        if (j < HIST_BINS - 1) {
-            const uint64_t ef = (bits >> 52) & 0x7ff;
-            uint64_t m = bits & ((1ull << 52) - 1);
-            if (ef) m |= 1ull << 52;
-            add += (unsigned long long)(m >> HIST_DROP);
+    // HIST_UNROLL regions a thread at a time, all their loads (flags and
+    // errors alike: the errors' cache lines are fetched anyway) issued
+    // before the first atomic; the integer sums do not depend on the order
+    const int64_t stride = blockDim.x;
+    for (int64_t c0 = s0 + threadIdx.x; c0 < s1; c0 += HIST_UNROLL * stride) {
+        uint8_t a[HIST_UNROLL];
+        uint64_t bits[HIST_UNROLL];
+#pragma unroll
+        for (int k = 0; k < HIST_UNROLL; ++k) {
+            const int64_t i = c0 + k * stride;
+            a[k] = i < s1 ? A_rel[i] : 0;
+            bits[k] = i < s1 ? __builtin_bit_cast(uint64_t, E[i]) : 0;
         }
-        atomicAdd(&lcs[j], add);
+#pragma unroll
+        for (int k = 0; k < HIST_UNROLL; ++k) {
+            if (!a[k]) continue;
+            const uint64_t key = bits[k] >> HIST_SHIFT;
+            uint64_t j = key >= kmax ? 0 : kmax - key;
+            if (j > HIST_BINS - 1) j = HIST_BINS - 1;
+            unsigned long long add = ONE;
+            if (j < HIST_BINS - 1) {
+                const uint64_t ef = (bits[k] >> 52) & 0x7ff;
+                uint64_t m = bits[k] & ((1ull << 52) - 1);
+                if (ef) m |= 1ull << 52;
+                add += (unsigned long long)(m >> HIST_DROP);
+            }
+            atomicAdd(&lcs[j], add);
+        }
     }
     __syncthreads();
     for (int b = threadIdx.x; b < HIST_BINS; b += blockDim.x) {
