@@ -243,6 +243,41 @@ def test_threshold_search_parity(ctx, seed, mem):
         np.testing.assert_array_equal(A.cpu().numpy(), A_rel)
 
 
+THRESH_SPREAD = [(seed, mem, sigma) for seed in (11, 12, 13) for mem in (0, 1)
+                 for sigma in (0.2, 1.0, 5.0)]
+
+
+@pytest.mark.parametrize("seed,mem,sigma", THRESH_SPREAD)
+def test_threshold_search_spread(ctx, seed, mem, sigma):
+    """Narrow and wide error spreads: many regions share a histogram bin
+    (undecided trials, exact passes) or the search runs long (direction
+    changes, P_max growth, its limits)."""
+    _say("threshold-spread", seed, mem, sigma)
+    rng = np.random.default_rng(seed * 7 + mem)
+    n = int(rng.integers(3000, 200000))
+    v = 1.8e-5
+    tau = float(10.0 ** rng.uniform(-8, -3))
+    # errors summing to 1.2 to 4 times the tolerance: searches that succeed
+    # after 1 or about 30 trials and ones that end at the direction-change
+    # or trial limits
+    E = rng.lognormal(sigma=sigma, size=n)
+    E *= float(rng.uniform(1.2, 4.0)) * tau * v / E.sum()
+    A_rel = (rng.uniform(size=n) < 0.8).astype(np.uint8)
+    e_it = oracle.csum(E)
+    e_f = float(rng.uniform(0, 0.5)) * tau * v
+    ok, A, t, trials = ctx.threshold_search(_dev(E), _dev(A_rel, torch.uint8), v,
+                                            e_it + e_f, e_it, tau, mem)
+    rok, rA, rt, rtrials, _ = oracle.threshold_search(E, A_rel, v, e_it + e_f, e_it,
+                                                      tau, mem)
+    assert (ok, trials) == (rok, rtrials)
+    if ok:
+        assert rel_close(t, rt, 1e-12)
+        diff = np.flatnonzero(A.cpu().numpy() != rA)
+        assert all(abs(E[i] - rt) <= 1e-12 * rt for i in diff)
+    else:
+        np.testing.assert_array_equal(A.cpu().numpy(), A_rel)
+
+
 @pytest.mark.parametrize("d,n", [(2, 1), (3, 2049), (5, 4096), (8, 10001)])
 def test_filter_split_bit_exact(ctx, d, n):
     _say("filter-split", d, n)
