@@ -478,13 +478,12 @@ int search(pg_context *ctx, int64_t n, const double *E, const uint8_t *A_rel,
     const int max_passes = (THR_MAX_TRIALS + TRIAL_DEPTH - 1) / TRIAL_DEPTH;
     hipStream_t st = ctx->stream;
     *out = SearchOut{};
-    // min / max E were left in ctx->dtot by the pass that preceded the call
-    HIP_OR_FAIL(ctx, launch_search_init(st, ctx->dstate, n, e_it, allowance,
-                                        mem, ctx->dtot));
-    // most trials are decided from the error histogram; exact passes take
+    // min / max E were left in ctx->dtot by the pass that preceded the call;
+    // most trials are decided from the error histogram, exact passes take
     // over from the first one it leaves open
     HIP_OR_FAIL(ctx, launch_search_hist(st, n, E, A_rel, ctx->dstate,
-                                        ctx->hcnt, ctx->hsum));
+                                        ctx->hcnt, ctx->hsum, e_it, allowance,
+                                        mem, ctx->dtot));
     int passes = 0;
     for (int bi = -1; bi < 3 && passes < max_passes; ++bi) {
         const int batch =

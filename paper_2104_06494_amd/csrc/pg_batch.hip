@@ -142,7 +142,8 @@ k_batch_hist_walk(const int32_t *__restrict__ order,
                   unsigned long long *__restrict__ sum) {
     const int slot = order[blockIdx.x];
     if (!inst[slot].searching || states[slot].done) return;
-    hist_walk(states + slot, cnt + (size_t)slot * HIST_BINS,
+    const SearchState init = states[slot];
+    hist_walk(init, states + slot, cnt + (size_t)slot * HIST_BINS,
               sum + (size_t)slot * HIST_BINS);
 }
 

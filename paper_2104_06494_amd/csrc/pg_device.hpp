@@ -399,14 +399,16 @@ __device__ inline void hist_segment(int64_t s0, int64_t s1,
 // lie in intervals; a trial is decided when both requirements come out the
 // same at both ends, with a relative margin of 1e-12 (far wider than the
 // rounding of the exact pass's sums). The first undecided trial is left to
-// the exact passes. Clears the histogram for the next search.
-__device__ inline void hist_walk(SearchState *__restrict__ gst,
+// the exact passes. The search starts from `init` and its state is left in
+// *gst. Clears the histogram for the next search.
+__device__ inline void hist_walk(const SearchState &init,
+                                 SearchState *__restrict__ gst,
                                  uint32_t *__restrict__ gcnt,
                                  unsigned long long *__restrict__ gsum) {
     __shared__ double pc[HIST_BINS + 1], pl[HIST_BINS + 1], pu[HIST_BINS + 1];
     __shared__ double csum[HIST_THREADS / 64 + 1][3];
     constexpr int PER = HIST_BINS / HIST_THREADS;
-    const uint64_t kmax = hist_key(gst->mx);
+    const uint64_t kmax = hist_key(init.mx);
     double c[PER], l[PER], u[PER];
     const int b0 = threadIdx.x * PER;
 #pragma unroll
@@ -483,7 +485,7 @@ __device__ inline void hist_walk(SearchState *__restrict__ gst,
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
-    SearchState st = *gst;
+    SearchState st = init;
     const double n = (double)st.n;
     while (!st.done) {
         if (st.trials >= THR_MAX_TRIALS) { st.done = 1; break; }

@@ -241,14 +241,15 @@ hipError_t launch_reduce_scan(hipStream_t st, int64_t nseg, SegPartials part,
                               const SearchState *state = nullptr,
                               SearchState *host_state = nullptr,
                               uint64_t *host_seq = nullptr, uint64_t seq = 0);
-hipError_t launch_search_init(hipStream_t st, SearchState *S, int64_t n,
-                              double e_it, double allowance, int mem,
-                              const Totals *minmax);
-// The search's error histogram and the trials it decides (k_hist +
-// k_hist_walk); cnt / sum hold HIST_BINS bins, zero on entry and left zero.
+// Starts a search in *S (first threshold e_it / n; min / max E from the
+// totals `minmax` of the pass before it) and decides the trials its error
+// histogram allows (k_hist + k_hist_walk); cnt / sum hold HIST_BINS bins,
+// zero on entry and left zero.
 hipError_t launch_search_hist(hipStream_t st, int64_t n, const double *E,
                               const uint8_t *A_rel, SearchState *S,
-                              uint32_t *cnt, unsigned long long *sum);
+                              uint32_t *cnt, unsigned long long *sum,
+                              double e_it, double allowance, int mem,
+                              const Totals *minmax);
 // One pass (TRIAL_DEPTH trials) of the search: k_trials + k_trial_walk; a
 // no-op once the search has ended. blk_part holds 2 TRIAL_M x TRIAL_BLOCKS
 // doubles.

@@ -72,21 +72,29 @@ k_reduce_scan(int64_t nseg, SegPartials part, uint32_t *__restrict__ offsets,
     }
 }
 
-__global__ void k_search_init(SearchState *__restrict__ S, int64_t n,
-                              double e_it, double allowance, int mem,
-                              const Totals *__restrict__ minmax) {
-    if (threadIdx.x != 0) return;
+// The state a search starts from (Algorithm 3): first threshold e_it / n,
+// P_max = 0.25, min / max E from the totals of the pass before it.
+__device__ inline SearchState search_start(int64_t n, double e_it,
+                                           double allowance, int mem,
+                                           const Totals &minmax) {
     SearchState s{};
     s.n = n;
     s.e_it = e_it;
     s.allowance = allowance;
     s.mem = mem;
-    s.mn = minmax->emin;
-    s.mx = minmax->emax;
+    s.mn = minmax.emin;
+    s.mx = minmax.emax;
     s.t = e_it / (double)n;
     s.P_max = 0.25;
     s.t_acc = -__builtin_huge_val();
-    *S = s;
+    return s;
+}
+
+__global__ void k_search_init(SearchState *__restrict__ S, int64_t n,
+                              double e_it, double allowance, int mem,
+                              const Totals *__restrict__ minmax) {
+    if (threadIdx.x != 0) return;
+    *S = search_start(n, e_it, allowance, mem, *minmax);
 }
 
 // Regions per histogram block for a list of more than 256 segments: about
@@ -102,7 +110,7 @@ __host__ __device__ inline int64_t hist_span(int64_t n) {
 // trials it decides (see hist_walk).
 __global__ void __launch_bounds__(LIST_THREADS)
 k_hist(int64_t n, const double *__restrict__ E,
-       const uint8_t *__restrict__ A_rel, const SearchState *__restrict__ S,
+       const uint8_t *__restrict__ A_rel, const Totals *__restrict__ minmax,
        uint32_t *__restrict__ cnt, unsigned long long *__restrict__ sum) {
     // lists of up to 256 segments: one block each; longer ones: blocks of
     // up to HIST_RANGE regions, about 256 of them
@@ -110,13 +118,17 @@ k_hist(int64_t n, const double *__restrict__ E,
     const int64_t span = nseg <= 256 ? SEG : hist_span(n);
     const int64_t s0 = (int64_t)blockIdx.x * span;
     const int64_t s1 = s0 + span < n ? s0 + span : n;
-    hist_segment(s0, s1, E, A_rel, hist_key(S->mx), cnt, sum);
+    hist_segment(s0, s1, E, A_rel, hist_key(minmax->emax), cnt, sum);
 }
 
+// Starts the search (as k_search_init) and walks the trials the histogram
+// decides.
 __global__ void __launch_bounds__(HIST_THREADS)
 k_hist_walk(SearchState *__restrict__ S, uint32_t *__restrict__ cnt,
-            unsigned long long *__restrict__ sum) {
-    hist_walk(S, cnt, sum);
+            unsigned long long *__restrict__ sum, int64_t n, double e_it,
+            double allowance, int mem, const Totals *__restrict__ minmax) {
+    const SearchState init = search_start(n, e_it, allowance, mem, *minmax);
+    hist_walk(init, S, cnt, sum);
 }
 
 // One pass over the list for the TRIAL_M thresholds of the current tree.
@@ -293,26 +305,25 @@ hipError_t launch_reduce_scan(hipStream_t st, int64_t nseg, SegPartials part,
     return hipGetLastError();
 }
 
-hipError_t launch_search_init(hipStream_t st, SearchState *S, int64_t n,
-                              double e_it, double allowance, int mem,
-                              const Totals *minmax) {
-    hipLaunchKernelGGL(k_search_init, dim3(1), dim3(64), 0, st, S, n, e_it,
-                       allowance, mem, minmax);
-    return hipGetLastError();
-}
-
 hipError_t launch_search_hist(hipStream_t st, int64_t n, const double *E,
                               const uint8_t *A_rel, SearchState *S,
-                              uint32_t *cnt, unsigned long long *sum) {
-    if (n <= 0) return hipSuccess;
+                              uint32_t *cnt, unsigned long long *sum,
+                              double e_it, double allowance, int mem,
+                              const Totals *minmax) {
+    if (n <= 0) {
+        hipLaunchKernelGGL(k_search_init, dim3(1), dim3(64), 0, st, S, n,
+                           e_it, allowance, mem, minmax);
+        return hipGetLastError();
+    }
     const int64_t nseg = seg_count(n, 0);
     const int64_t span = nseg <= 256 ? SEG : hist_span(n);
     hipLaunchKernelGGL(k_hist, dim3((unsigned)((n + span - 1) / span)),
-                       dim3(LIST_THREADS), 0, st, n, E, A_rel, S, cnt, sum);
+                       dim3(LIST_THREADS), 0, st, n, E, A_rel, minmax, cnt,
+                       sum);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_hist_walk, dim3(1), dim3(HIST_THREADS), 0, st, S, cnt,
-                       sum);
+                       sum, n, e_it, allowance, mem, minmax);
     return hipGetLastError();
 }
 
