@@ -1074,6 +1074,10 @@ int pg_integrate(pg_context *ctx, const pg_integrand *f, const double *lo,
     if (tr) std::fclose(tr);
     tr = nullptr;
     if (timing) {
+        // the stream has drained, but a trailing marker can still be
+        // reported as pending for a moment: wait for the last event itself
+        (void)hipEventSynchronize(
+            ctx->events[5 * (it - 1) + (timing > 1 ? 4 : 1)]);
         for (int q = 0; q < it; ++q) {
             hipEvent_t *ev = &ctx->events[5 * q];
             float ms;

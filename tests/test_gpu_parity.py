@@ -399,6 +399,24 @@ def test_runs_are_bitwise_reproducible(ctx):
         (r2.estimate, r2.error, r2.regions_evaluated)
 
 
+def test_integrate_on_a_side_stream(ctx):
+    """A run queued on another torch stream (the context follows the current
+    stream; the host polls the totals the reduce kernels leave in mapped
+    memory) is the same run, with or without timing events."""
+    _say("side-stream")
+    wl = W.gaussian_d5()
+    r0 = ctx.integrate_workload(wl, rel_tol=1e-5)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        r1 = ctx.integrate_workload(wl, rel_tol=1e-5)
+        r2 = ctx.integrate_workload(wl, rel_tol=1e-5, timing=2)
+    side.synchronize()
+    for r in (r1, r2):
+        assert (r.status, r.iterations, r.regions_evaluated, r.estimate, r.error) == \
+            (r0.status, r0.iterations, r0.regions_evaluated, r0.estimate, r0.error)
+    assert all(x > 0 for x in r2.phase_ms) and r2.phase_ms[0] < 1e3
+
+
 def test_integrate_invalid_arguments(ctx):
     _say("integrate-invalid")
     import paper_2104_06494_amd as pg
