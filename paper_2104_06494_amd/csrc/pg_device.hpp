@@ -405,7 +405,10 @@ __device__ inline void hist_walk(const SearchState &init,
                                  SearchState *__restrict__ gst,
                                  uint32_t *__restrict__ gcnt,
                                  unsigned long long *__restrict__ gsum) {
-    __shared__ double pc[HIST_BINS + 1], pl[HIST_BINS + 1], pu[HIST_BINS + 1];
+    // bin j's bounds for a trial: {count above, lower error sum above} and
+    // {count above, upper error sum above}, the sums already widened by the
+    // margin, so a trial reads two 16-byte words
+    __shared__ double2 plo[HIST_BINS + 1], phi[HIST_BINS + 1];
     __shared__ double csum[HIST_THREADS / 64 + 1][3];
     constexpr int PER = HIST_BINS / HIST_THREADS;
     const uint64_t kmax = hist_key(init.mx);
@@ -470,17 +473,15 @@ __device__ inline void hist_walk(const SearchState &init,
                d = csum[wave][2] + ex[2];
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            pc[b0 + q] = a;
-            pl[b0 + q] = b;
-            pu[b0 + q] = d;
+            plo[b0 + q] = make_double2(a, b * (1.0 - 1e-12));
+            phi[b0 + q] = make_double2(a, d * (1.0 + 1e-12));
             a += c[q];
             b += l[q];
             d += u[q];
         }
         if (threadIdx.x == HIST_THREADS - 1) {
-            pc[HIST_BINS] = a;
-            pl[HIST_BINS] = b;
-            pu[HIST_BINS] = d;
+            plo[HIST_BINS] = make_double2(a, b * (1.0 - 1e-12));
+            phi[HIST_BINS] = make_double2(a, d * (1.0 + 1e-12));
         }
     }
     __syncthreads();
@@ -498,10 +499,11 @@ __device__ inline void hist_walk(const SearchState &init,
         } else {
             uint64_t j = kmax - kt;
             if (j > HIST_BINS - 1) j = HIST_BINS - 1;
-            c_lo = pc[j];
-            c_hi = pc[j + 1];
-            s_lo = pl[j] * (1.0 - 1e-12);
-            s_hi = pu[j + 1] * (1.0 + 1e-12);
+            const double2 lo2 = plo[j], hi2 = phi[j + 1];
+            c_lo = lo2.x;
+            c_hi = hi2.x;
+            s_lo = lo2.y;
+            s_hi = hi2.y;
         }
         bool mem_ok, acc_ok = false;
         if (n - c_hi > 0.5 * n) mem_ok = true;
