@@ -95,6 +95,26 @@ typedef enum {
     PG_ERR_NULL4 = 1
 } pg_error_rule;
 
+/*
+ * How the threshold search (Algorithm 3) relaxes its accuracy requirement.
+ * The search starts with P_max = 0.25 of the error the finished regions may
+ * still carry and gives up after 10 direction changes or 64 trials.
+ *  PG_PMAX_EVERY_CHANGE  P_max grows by 0.10 at every change of search
+ *                        direction, up to 0.95, in every search: the rule as
+ *                        Section 3.5.3 states it (the default).
+ *  PG_PMAX_UNDER_MEMORY  a departure from Section 3.5.3: P_max grows only
+ *                        in searches run because the live list would
+ *                        overflow its cap (trigger (b) of Section 3.5.2);
+ *                        searches run because the estimate's digits have
+ *                        settled keep 0.25. It commits less error to
+ *                        finished regions, and so ends fewer runs with every
+ *                        region finished and the tolerance unmet.
+ */
+typedef enum {
+    PG_PMAX_EVERY_CHANGE = 0,
+    PG_PMAX_UNDER_MEMORY = 1
+} pg_pmax_relax;
+
 typedef struct pg_context pg_context;
 
 typedef struct {
@@ -119,11 +139,13 @@ typedef struct {
                                  costs the run a few microseconds. */
     const char *trace_path;   /* non-NULL: write the decision trace (below) */
     int error_rule;           /* pg_error_rule */
+    int pmax_relax;           /* pg_pmax_relax */
 } pg_options;
 
-/* Default options: rel_tol 1e-3, abs_tol 1e-20, g = 4, it_max = 100, both
-   filters on, cap = capacity, no timing, no trace, error rule
-   PG_ERR_RAW. */
+/* Default options (the inputs of Algorithm 2 and the user flag of Section
+   3.5.1): rel_tol 1e-3, abs_tol 1e-20, g = 4, it_max = 100, both filters
+   on, cap = capacity, no timing, no trace, error rule PG_ERR_RAW, P_max
+   rule PG_PMAX_EVERY_CHANGE. A zero-filled struct holds the same rules. */
 void pg_default_options(pg_options *opt);
 
 typedef struct {
@@ -147,12 +169,16 @@ typedef struct {
 /*
  * Bytes of device workspace for lists of up to `capacity` regions of up to
  * `dim_max` dimensions (two ping-pong region lists plus V, E, K, A,
- * parents and reduction scratch).
+ * parents and reduction scratch). Section 4 sets memory up once, outside
+ * the timed integration; so does this library: nothing is allocated per
+ * iteration. Returns 0 for a dimension outside PG_DIM_MIN..PG_DIM_MAX or a
+ * capacity below 2.
  */
 size_t pg_workspace_bytes(int dim_max, int64_t capacity);
 
 /*
- * Create a context on HIP device `device`. `workspace` is device memory of
+ * Create a context on HIP device `device`: the once-only set-up that Section
+ * 4 keeps out of the timed integration. `workspace` is device memory of
  * at least pg_workspace_bytes(dim_max, capacity) bytes owned by the caller
  * (for example a PyTorch tensor's storage), or NULL to let the context
  * allocate (and later free) it; a caller's workspace must be 256-byte
@@ -163,6 +189,9 @@ size_t pg_workspace_bytes(int dim_max, int64_t capacity);
 int pg_context_create(int device, int dim_max, int64_t capacity,
                       void *workspace, size_t ws_bytes, void *stream,
                       pg_context **out);
+/* Waits for the context's stream, then frees what the context allocated
+   (not a caller's workspace). NULL is ignored. Call it while the HIP
+   runtime is still up, not from a process-exit handler. */
 void pg_context_destroy(pg_context *ctx);
 /* Replace the stream work is queued on (a hipStream_t, NULL = null stream). */
 int pg_context_set_stream(pg_context *ctx, void *stream);
@@ -178,7 +207,8 @@ const char *pg_last_error(const pg_context *ctx);
  * PG_EUNSUPPORTED, PG_EHIP.
  *
  * Decision trace (when opt->trace_path is set), little endian:
- *   header  char magic[8] = "PGTRACE1"; int32 d; int32 family; int64 0, 0
+ *   header  char magic[8] = "PGTRACE1"; int32 d; int32 family;
+ *           int64 pmax_relax, error_rule (the run's rules)
  *   per iteration:
  *     int64 it, n, n_active; int32 thr_invoked, thr_ok, thr_trials,
  *     terminal (-1 = continues, else the pg_status the run ends with);
@@ -254,10 +284,12 @@ int pg_integrate_batch_grad(pg_context *ctx, int family, int dim, int B,
                             double *grad, pg_leaves *leaves);
 
 /*
- * View of the live region list as the last pg_integrate left it: the n
- * regions of its last iteration with their V, (refined) E, split axis K and
- * rel-err flags A. Device pointers, valid until the next call that uses the
- * context.
+ * View of the live region list H of Algorithm 2 as the last pg_integrate
+ * left it: the n regions of its last iteration with their V, (refined) E,
+ * split axis K and rel-err flags A (Section 3.1 names these lists). Device
+ * pointers into the context's workspace, valid until the next call that
+ * uses the context; ld is the context's capacity. PG_EINVAL for NULL
+ * arguments; n is 0 before the first run.
  */
 typedef struct {
     int dim;
@@ -291,9 +323,12 @@ int pg_evaluate_rule(pg_context *ctx, const pg_integrand *f, int error_rule,
 
 /*
  * The integrand alone: y[i] = f(x_i) for n points x_i with coordinates
- * x[k * ld + i] (device arrays). The same inlined code as EVALUATE uses;
- * for checking an integrand and for counting its cost. Queued on the
- * context's stream.
+ * x[k * ld + i] (device arrays). Section 3.2 evaluates f at the rule's
+ * points; this is the same inlined code EVALUATE uses, for checking an
+ * integrand and for counting its cost (the FLOP per evaluation in the
+ * evaluate roofline). Queued on the context's stream. PG_EINVAL for bad
+ * n / ld or NULL arrays, PG_EUNSUPPORTED for a family or dimension not
+ * built.
  */
 int pg_integrand_values(pg_context *ctx, const pg_integrand *f, int64_t n,
                         const double *x, int64_t ld, double *y);
@@ -313,25 +348,32 @@ int pg_classify(pg_context *ctx, int64_t n, int paired, const double *V,
                 int relerr_filter, uint8_t *A, double *sums);
 
 /*
- * THRESHOLD-CLASSIFY (Algorithm 3) on n regions with errors E and rel-err
- * flags A_rel: searches t such that A = A_rel AND (E > t) finishes more than
- * half of the regions with finished error <= P_max (tau |v_tot| - e_f),
- * e_f = e_tot - e_it. P_max starts at 0.25 and, only under
- * memory_pressure, grows by 0.10 per direction change (max 0.95). At most
- * 64 trials and 10 direction changes. Returns 1 in *ok with t and A_out
- * (device, n bytes) on success; 0 and A_out = A_rel on failure. Blocks.
+ * THRESHOLD-CLASSIFY (Algorithm 3, Section 3.5.3) on n regions with errors
+ * E and rel-err flags A_rel: searches t such that A = A_rel AND (E > t)
+ * finishes more than half of the regions with finished error <= P_max
+ * (tau |v_tot| - e_f), e_f = e_tot - e_it. P_max starts at 0.25; with
+ * relax != 0 it grows by 0.10 per direction change (max 0.95), as Section
+ * 3.5.3 states; with relax = 0 it stays 0.25 (pg_integrate passes 0 only
+ * under PG_PMAX_UNDER_MEMORY for a search the memory trigger did not
+ * start). At most 64 trials and 10 direction changes. Returns 1 in *ok
+ * with t and A_out (device, n bytes) on success; 0 and A_out = A_rel on
+ * failure. Blocks.
  */
 int pg_threshold_search(pg_context *ctx, int64_t n, const double *E,
                         const uint8_t *A_rel, double v_tot, double e_tot,
-                        double e_it, double rel_tol, int memory_pressure,
+                        double e_it, double rel_tol, int relax,
                         uint8_t *A_out, int *ok, double *t, int *trials);
 
 /*
- * FILTER + parent update + SPLIT: stable compaction of the regions with
+ * FILTER + parent update + SPLIT (the last three steps of Algorithm 2's
+ * loop; Section 3.4 bisects every active region): stable compaction of the
+ * regions with
  * A[i] = 1; the j-th survivor is bisected along axis K[i] into the lower
  * half at index j and the upper half at index j + n_active of the output
  * list (ld_out >= 2 n_active), and Vp[j] = V[i]. Writes *n_active (host).
- * Blocks until *n_active is known.
+ * Blocks until *n_active is known. Device arrays: lo, w (ld_in >= n), K, V,
+ * A in; lo_out, w_out, Vp out (must not overlap the inputs). PG_EINVAL for
+ * a bad dimension, n / ld or ld_out, or a NULL array.
  */
 int pg_filter_split(pg_context *ctx, int dim, int64_t n, const double *lo,
                     const double *w, int64_t ld_in, const uint8_t *K,

@@ -81,7 +81,7 @@ def lib():
     L.oracle_integrate.restype = C.c_int
     L.oracle_integrate.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, C.c_double,
                                    C.c_double, C.c_int, C.c_int, C.c_int,
-                                   C.c_int, C.c_int, C.c_int64, C.c_char_p, _dp,
+                                   C.c_int, C.c_int, C.c_int, C.c_int64, C.c_char_p, _dp,
                                    np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS"),
                                    C.POINTER(ReplayStats), C.c_void_p, C.c_void_p,
                                    C.c_void_p]
@@ -115,6 +115,10 @@ def rule(d: int):
 
 
 ERROR_RULE = {"raw": 0, "null4": 1}
+
+# P_max relaxation of the threshold search: at every direction change of
+# every search (Section 3.5.3) or only in searches under memory pressure
+PMAX_RELAX = {"paper": 0, "memory": 1}
 
 
 def null_rules(d: int) -> np.ndarray:
@@ -181,9 +185,10 @@ def csum(x, mask=None) -> float:
     return lib().oracle_sum(len(x), x, _ptr(m))
 
 
-def threshold_search(E, A_rel, v_tot, e_tot, e_it, tau_rel,
-                     memory_pressure=False):
-    """Threshold-Classify (Algorithm 3). Returns (ok, A, t, trials, tried_ts)."""
+def threshold_search(E, A_rel, v_tot, e_tot, e_it, tau_rel, relax=True):
+    """Threshold-Classify (Algorithm 3); with relax, P_max grows by 0.10 at
+    each change of direction up to 0.95 (Section 3.5.3), else it stays at
+    0.25. Returns (ok, A, t, trials, tried_ts)."""
     E = _f64(E)
     A_rel = np.ascontiguousarray(A_rel, dtype=np.uint8)
     A = np.zeros(len(E), np.uint8)
@@ -191,7 +196,7 @@ def threshold_search(E, A_rel, v_tot, e_tot, e_it, tau_rel,
     tr = C.c_int()
     tried = np.zeros(64)
     ok = lib().oracle_threshold_search(len(E), E, A_rel, v_tot, e_tot, e_it,
-                                       tau_rel, int(bool(memory_pressure)), A,
+                                       tau_rel, int(bool(relax)), A,
                                        C.byref(t), C.byref(tr),
                                        _ptr(tried))
     return bool(ok), A, t.value, tr.value, tried[:tr.value].copy()
@@ -247,7 +252,7 @@ def integrate(family: str, d: int, params, lo=None, hi=None, rel_tol=1e-3,
               abs_tol=1e-20, init_splits=4, max_iters=100, relerr_filter=1,
               threshold_filter=1, max_regions=1 << 22,
               replay_path: str | None = None, grad: bool = False,
-              error_rule: str = "raw") -> OracleResult:
+              error_rule: str = "raw", pmax_relax: str = "paper") -> OracleResult:
     """PAGANI main loop (Algorithm 2), free mode or replaying a GPU trace.
     With grad=True also the derivative of the estimate with respect to the
     parameters over the partition the run ends on (its leaves: every region
@@ -264,7 +269,8 @@ def integrate(family: str, d: int, params, lo=None, hi=None, rel_tol=1e-3,
     rc = lib().oracle_integrate(FAMILY_ID[family], d, _f64(params), lo, hi,
                                 rel_tol, abs_tol, init_splits, max_iters,
                                 relerr_filter, threshold_filter,
-                                ERROR_RULE[error_rule], max_regions,
+                                ERROR_RULE[error_rule], PMAX_RELAX[pmax_relax],
+                                max_regions,
                                 replay_path.encode() if replay_path else None,
                                 out_d, out_i, C.byref(rs), _ptr(g), _ptr(ga), _ptr(lv))
     if rc:
@@ -316,4 +322,4 @@ __all__ = ["lib", "npoints", "rule", "f", "eval_regions", "two_level",
            "classify", "csum", "threshold_search", "filter_split",
            "uniform_split", "integrate", "integrate_workload", "OracleResult",
            "grad_f", "grad_regions", "null_rules", "ERROR_RULE",
-           "RegionEval", "FAMILY_ID", "STATUS"]
+           "RegionEval", "FAMILY_ID", "STATUS", "PMAX_RELAX"]

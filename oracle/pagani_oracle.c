@@ -29,8 +29,10 @@
  *   R5  classification (Section 3.5.1, Lemma 1): finished iff E <= tau |V|;
  *   R6  threshold search (Algorithm 3) with the directions fixed by the
  *       Figure 3 narrative, the accuracy requirement measured against the
- *       error finished regions may still carry, P_max relaxed only under
- *       memory pressure, 10 direction changes / 64 trials at most;
+ *       error finished regions may still carry, P_max relaxed at every
+ *       direction change as Section 3.5.3 states (or, as an option that
+ *       departs from it, only under memory pressure), 10 direction changes /
+ *       64 trials at most;
  *   R7  filter/split order: stable compaction; children of the j-th active
  *       region go to j (lower half) and j + n_active (upper half);
  *   R9  optional error estimate from four null rules (Section 3.2 compares
@@ -717,13 +719,12 @@ double oracle_sum(long n, const double *x, const uint8_t *mask)
  *   convergence, which the literal comparison with e_b does not prevent);
  *   memory fails  -> raise t halfway to max(E);
  *   accuracy fails-> lower t halfway to min(E);
- *   when the search runs because the list would overflow its memory cap
- *   (memory_pressure), each change of direction adds 0.10 to P_max (at
- *   most 0.95): Section 3.5.2 presents giving up accuracy budget as the
- *   price of being able to continue at all, which only that case pays;
- *   when it runs because the estimate's digits have settled, P_max stays
- *   at 0.25. The search gives up after 10 direction changes or 64 trials
- *   and then leaves A_rel unchanged.
+ *   with relax set, each change of direction adds 0.10 to P_max (at most
+ *   0.95), as Section 3.5.3 states; with relax clear P_max stays at 0.25
+ *   (the caller decides: every search relaxes under the paper's rule, only
+ *   searches under memory pressure under the memory-only option). The
+ *   search gives up after 10 direction changes or 64 trials and then
+ *   leaves A_rel unchanged.
  * Returns 1 on success (Aout and *t_out set), 0 on failure (Aout = A_rel).
  * ---------------------------------------------------------------------- */
 #define OR_THR_MAX_TRIALS 64
@@ -731,7 +732,7 @@ double oracle_sum(long n, const double *x, const uint8_t *mask)
 
 int oracle_threshold_search(long s_it, const double *E, const uint8_t *A_rel,
                             double v_tot, double e_tot, double e_it,
-                            double tau_rel, int memory_pressure,
+                            double tau_rel, int relax,
                             uint8_t *Aout, double *t_out,
                             int *trials_out, double *tried /* [64] or NULL */)
 {
@@ -769,7 +770,7 @@ int oracle_threshold_search(long s_it, const double *E, const uint8_t *A_rel,
         }
         if (last_dir != 0 && dir != last_dir) {
             dir_changes++;
-            if (memory_pressure) {
+            if (relax) {
                 P_max = P_max + 0.10;
                 if (P_max > 0.95) P_max = 0.95;
             }
@@ -875,6 +876,8 @@ typedef struct {
  *   out_d[0] estimate, [1] error, [2] evaluate seconds, [3] total seconds
  *   out_i[0] status, [1] iterations, [2] regions evaluated, [3] f evals,
  *        [4] peak regions, [5] threshold invocations, [6] threshold trials
+ * pmax_relax: 0 = P_max grows at every direction change of every search
+ * (Section 3.5.3); 1 = only in searches started by the memory trigger.
  * When replay_path is set the run follows the decisions recorded in that
  * trace and fills *rs; otherwise rs may be NULL.
  * ---------------------------------------------------------------------- */
@@ -902,6 +905,7 @@ int oracle_integrate(int family, int d, const double *par,
                      const double *a, const double *b,
                      double tau_rel, double tau_abs, int g, int it_max,
                      int relerr_filter, int threshold_filter, int err_rule,
+                     int pmax_relax,
                      int64_t max_regions, const char *replay_path,
                      double *out_d, int64_t *out_i, or_replay_stats *rs,
                      double *grad, double *grad_abs, double *leaf_v)
@@ -927,6 +931,7 @@ int oracle_integrate(int family, int d, const double *par,
     if (d < 1 || d > OR_DMAX || g < 1 || it_max < 1) return OR_EINVAL;
     if (err_rule != 0 && (err_rule != 1 || d < 2 || d > OR_NULL_DMAX))
         return OR_EINVAL;
+    if (pmax_relax != 0 && pmax_relax != 1) return OR_EINVAL;
     if (!(tau_rel > 0.0) && !(tau_abs > 0.0)) return OR_EINVAL;
     for (k = 0; k < d; k++) if (!(a[k] < b[k])) return OR_EINVAL;
     s = 1;
@@ -942,7 +947,8 @@ int oracle_integrate(int family, int d, const double *par,
         if (!tr) return OR_EREPLAY;
         if (fread(magic, 1, 8, tr) != 8 || memcmp(magic, "PGTRACE1", 8) ||
             fread(hd, 4, 2, tr) != 2 || fread(res, 8, 2, tr) != 2 ||
-            hd[0] != d || hd[1] != family) {
+            hd[0] != d || hd[1] != family ||
+            res[0] != pmax_relax || res[1] != err_rule) {
             fclose(tr);
             return OR_EREPLAY;
         }
@@ -1089,8 +1095,8 @@ int oracle_integrate(int family, int d, const double *par,
         if (invoke) {
             thr_calls++;
             ok = oracle_threshold_search(s, E, A_rel, v_tot, e_tot, e, tau_rel,
-                                         2 * n_rel > cap, A, &t, &trials,
-                                         NULL);
+                                         pmax_relax == 0 || 2 * n_rel > cap,
+                                         A, &t, &trials, NULL);
             thr_trials += trials;
             if (tr) {
                 if (ok != (rec.thr_ok != 0) || trials != rec.thr_trials) {

@@ -18,6 +18,9 @@ FAMILY_ID = {"product_peak": 0, "gaussian": 1, "oscillatory": 2,
              "corner_peak": 3, "monomial": 4, "c0": 5, "discontinuous": 6,
              "box": 7}
 ERROR_RULE = {"raw": 0, "null4": 1}
+# P_max relaxation of the threshold search: at every direction change
+# (Section 3.5.3, the default) or only in searches under memory pressure
+PMAX_RELAX = {"paper": 0, "memory": 1}
 STATUS = {0: "OK", 1: "MAX_ITERS", 2: "MEMORY_EXHAUSTED", 3: "NO_ACTIVE",
           -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EUNSUPPORTED"}
 
@@ -39,7 +42,8 @@ class Options(C.Structure):
                 ("init_splits", C.c_int), ("max_iters", C.c_int),
                 ("relerr_filter", C.c_int), ("threshold_filter", C.c_int),
                 ("max_regions", C.c_int64), ("timing", C.c_int),
-                ("trace_path", C.c_char_p), ("error_rule", C.c_int)]
+                ("trace_path", C.c_char_p), ("error_rule", C.c_int),
+                ("pmax_relax", C.c_int)]
 
 
 class Result(C.Structure):

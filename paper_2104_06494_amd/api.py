@@ -6,7 +6,10 @@ include/pagani.h for the layouts).
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import sys
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -35,6 +38,14 @@ def _error_rule(rule):
             raise ValueError(f"error_rule must be one of {sorted(L.ERROR_RULE)}")
         return L.ERROR_RULE[rule]
     return int(rule)
+
+
+def _pmax_relax(mode):
+    if isinstance(mode, str):
+        if mode not in L.PMAX_RELAX:
+            raise ValueError(f"pmax_relax must be one of {sorted(L.PMAX_RELAX)}")
+        return L.PMAX_RELAX[mode]
+    return int(mode)
 
 
 def _integrand(family, d, params):
@@ -98,13 +109,23 @@ class Context:
         if rc != 0:
             raise PaganiError(rc, "pg_context_create failed")
         self.h = h
+        _live.add(self)
 
     def close(self):
+        """Destroys the C context (waits for its stream, frees its pinned
+        host memory). Idempotent; contexts still open when the interpreter
+        exits are closed by an exit handler while HIP is still up."""
         if getattr(self, "h", None):
-            self.lib.pg_context_destroy(self.h)
+            with torch.cuda.device(self.device):
+                self.lib.pg_context_destroy(self.h)
             self.h = None
 
     def __del__(self):
+        # during interpreter shutdown the HIP runtime may already be going
+        # away: leave the context to the process exit instead of calling
+        # into HIP from a finaliser
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -142,9 +163,13 @@ class Context:
     def integrate(self, family, d, params, lo=None, hi=None, rel_tol=1e-3,
                   abs_tol=1e-20, init_splits=4, max_iters=100, relerr_filter=1,
                   threshold_filter=1, max_regions=0, timing=False,
-                  trace_path=None, error_rule="raw") -> IntegrateResult:
+                  trace_path=None, error_rule="raw",
+                  pmax_relax="paper") -> IntegrateResult:
         """Algorithm 2 over the box [lo, hi] (default unit cube). error_rule
-        "raw" (|R7 - R5|) or "null4" (the four-null-rule estimate)."""
+        "raw" (|R7 - R5|) or "null4" (the four-null-rule estimate);
+        pmax_relax "paper" (P_max grows at every direction change of a
+        threshold search, Section 3.5.3) or "memory" (only in searches under
+        memory pressure)."""
         self._bind_stream()
         f, keep = _integrand(family, d, params)
         lo = np.zeros(d) if lo is None else np.asarray(lo, dtype=np.float64)
@@ -161,6 +186,7 @@ class Context:
         o.timing = 2 if timing is True else int(timing)
         o.trace_path = trace_path.encode() if trace_path else None
         o.error_rule = _error_rule(error_rule)
+        o.pmax_relax = _pmax_relax(pmax_relax)
         r = L.Result()
         with torch.cuda.device(self.device):
             rc = self.lib.pg_integrate(self.h, C.byref(f), clo, chi, C.byref(o),
@@ -172,19 +198,20 @@ class Context:
     def integrate_batch(self, family, d, params, rel_tol, abs_tol=None,
                         lo=None, hi=None, init_splits=4, max_iters=100,
                         relerr_filter=1, threshold_filter=1, max_regions=0,
-                        error_rule="raw"):
+                        error_rule="raw", pmax_relax="paper"):
         """Algorithm 2 for B integrals of one family at once: params is
         [B, n_params], rel_tol a scalar or [B], abs_tol None (1e-20), a
         scalar or [B]; all share the box [lo, hi] and the options, and
         max_regions is the cap of each. Returns a list of B results."""
         return self._batch(family, d, params, rel_tol, abs_tol, lo, hi, init_splits,
                            max_iters, relerr_filter, threshold_filter, max_regions,
-                           error_rule=error_rule)[0]
+                           error_rule=error_rule, pmax_relax=pmax_relax)[0]
 
     def integrate_batch_grad(self, family, d, params, rel_tol, abs_tol=None,
                              lo=None, hi=None, init_splits=4, max_iters=100,
                              relerr_filter=1, threshold_filter=1, max_regions=0,
-                             leaves_capacity=0, error_rule="raw"):
+                             leaves_capacity=0, error_rule="raw",
+                             pmax_relax="paper"):
         """integrate_batch plus dI/dparams of every integral over its final
         partition: returns (results, grad [B, n_params] numpy, leaves). With
         leaves_capacity > 0, leaves is a dict of device tensors lo, w [d, n]
@@ -192,12 +219,12 @@ class Context:
         return self._batch(family, d, params, rel_tol, abs_tol, lo, hi, init_splits,
                            max_iters, relerr_filter, threshold_filter, max_regions,
                            grad=True, leaves_capacity=leaves_capacity,
-                           error_rule=error_rule)
+                           error_rule=error_rule, pmax_relax=pmax_relax)
 
     def integrate_grad(self, family, d, params, lo=None, hi=None, rel_tol=1e-3,
                        abs_tol=1e-20, init_splits=4, max_iters=100, relerr_filter=1,
                        threshold_filter=1, max_regions=0, leaves_capacity=0,
-                       error_rule="raw"):
+                       error_rule="raw", pmax_relax="paper"):
         """One integral and its parameter derivative through the C entry
         point pg_integrate_grad: returns (result, grad [n_params], leaves)."""
         self._bind_stream()
@@ -213,6 +240,7 @@ class Context:
         o.relerr_filter, o.threshold_filter = int(relerr_filter), int(threshold_filter)
         o.max_regions = int(max_regions)
         o.error_rule = _error_rule(error_rule)
+        o.pmax_relax = _pmax_relax(pmax_relax)
         g = np.zeros(f.n_params)
         lv, lt = self._leaves(d, leaves_capacity)
         r = L.Result()
@@ -244,7 +272,7 @@ class Context:
 
     def _batch(self, family, d, params, rel_tol, abs_tol, lo, hi, init_splits,
                max_iters, relerr_filter, threshold_filter, max_regions, grad=False,
-               leaves_capacity=0, error_rule="raw"):
+               leaves_capacity=0, error_rule="raw", pmax_relax="paper"):
         self._bind_stream()
         P = np.ascontiguousarray(np.atleast_2d(np.asarray(params, dtype=np.float64)))
         B, npar = P.shape
@@ -266,6 +294,7 @@ class Context:
         o.relerr_filter, o.threshold_filter = int(relerr_filter), int(threshold_filter)
         o.max_regions = int(max_regions)
         o.error_rule = _error_rule(error_rule)
+        o.pmax_relax = _pmax_relax(pmax_relax)
         res = (L.Result * B)()
         fam = L.FAMILY_ID[family] if isinstance(family, str) else int(family)
         g = np.zeros((B, npar)) if grad else None
@@ -285,12 +314,14 @@ class Context:
         results = [IntegrateResult(**res[b].as_dict()) for b in range(B)]
         return results, g, self._leaves_view(lv, lt)
 
-    def integrate_batch_workload(self, wl, count=None, grad=False, leaves_capacity=0):
+    def integrate_batch_workload(self, wl, count=None, grad=False, leaves_capacity=0,
+                                 **kw):
         """integrate_batch (or integrate_batch_grad with grad=True) over a
-        batched workload (its first `count` integrals if given)."""
+        batched workload (its first `count` integrals if given); keyword
+        arguments (error_rule, pmax_relax) go to the integrator."""
         B = wl.B if count is None else int(count)
         fn = self.integrate_batch
-        kw = {}
+        kw = dict(kw)
         if grad:
             fn = self.integrate_batch_grad
             kw["leaves_capacity"] = leaves_capacity
@@ -379,8 +410,9 @@ class Context:
         return A, list(sums)
 
     def threshold_search(self, E, A_rel, v_tot, e_tot, e_it, rel_tol,
-                         memory_pressure=False):
-        """THRESHOLD-CLASSIFY (Algorithm 3). Returns (ok, A, t, trials)."""
+                         relax=True):
+        """THRESHOLD-CLASSIFY (Algorithm 3); relax: P_max grows at each
+        direction change (Section 3.5.3). Returns (ok, A, t, trials)."""
         self._bind_stream()
         _check_f64(E, "E", self.device)
         _check_u8(A_rel, "A_rel", self.device)
@@ -388,7 +420,7 @@ class Context:
         ok, t, tr = C.c_int(), C.c_double(), C.c_int()
         rc = self.lib.pg_threshold_search(self.h, E.numel(), _ptr(E), _ptr(A_rel),
                                           float(v_tot), float(e_tot), float(e_it),
-                                          float(rel_tol), int(bool(memory_pressure)),
+                                          float(rel_tol), int(bool(relax)),
                                           _ptr(A), C.byref(ok), C.byref(t),
                                           C.byref(tr))
         if rc:
@@ -418,6 +450,20 @@ class Context:
 
 
 _default_ctx = {}
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    """Closes every context still open (the cached ones included) when the
+    interpreter exits: Python runs this before it tears its modules down and
+    before the C runtime's exit handlers (HIP's, a profiler's) run."""
+    _default_ctx.clear()
+    for ctx in list(_live):
+        try:
+            ctx.close()
+        except Exception:
+            pass
 
 
 def context(capacity=1 << 22, dim_max=L.PG_DIM_MAX) -> Context:

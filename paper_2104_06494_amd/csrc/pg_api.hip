@@ -471,7 +471,7 @@ struct CountReq {
 };
 
 int search(pg_context *ctx, int64_t n, const double *E, const uint8_t *A_rel,
-           double v_tot, double e_tot, double e_it, double tau, int mem,
+           double v_tot, double e_tot, double e_it, double tau, int relax,
            const CountReq *count, SearchOut *out) {
     const double e_b = e_tot - tau * std::fabs(v_tot);
     const double allowance = e_it - e_b;      // = tau |v_tot| - e_f
@@ -483,7 +483,7 @@ int search(pg_context *ctx, int64_t n, const double *E, const uint8_t *A_rel,
     // over from the first one it leaves open
     HIP_OR_FAIL(ctx, launch_search_hist(st, n, E, A_rel, ctx->dstate,
                                         ctx->hcnt, ctx->hsum, e_it, allowance,
-                                        mem, ctx->dtot));
+                                        relax, ctx->dtot));
     int passes = 0;
     for (int bi = -1; bi < 3 && passes < max_passes; ++bi) {
         const int batch =
@@ -528,6 +528,23 @@ int validate_list(pg_context *ctx, int64_t n, int64_t ld) {
     if (n > ctx->cap)
         return fail(ctx, PG_ENOMEM, "n = %lld above the context capacity %lld",
                     (long long)n, (long long)ctx->cap);
+    return PG_OK;
+}
+
+// Whether a threshold search relaxes P_max at its direction changes
+// (Section 3.5.3 relaxes it in every search; the memory-only option only in
+// searches triggered because the list would overflow its cap).
+int relax_pmax(const pg_options &o, bool memory_trigger) {
+    return o.pmax_relax == PG_PMAX_EVERY_CHANGE || memory_trigger ? 1 : 0;
+}
+
+// Option checks shared by the single and the batched drivers.
+int check_rules(pg_context *ctx, const pg_options &o) {
+    if (o.error_rule != PG_ERR_RAW && o.error_rule != PG_ERR_NULL4)
+        return fail(ctx, PG_EINVAL, "unknown error rule %d", o.error_rule);
+    if (o.pmax_relax != PG_PMAX_EVERY_CHANGE &&
+        o.pmax_relax != PG_PMAX_UNDER_MEMORY)
+        return fail(ctx, PG_EINVAL, "unknown P_max rule %d", o.pmax_relax);
     return PG_OK;
 }
 
@@ -770,7 +787,7 @@ int pg_classify(pg_context *ctx, int64_t n, int paired, const double *V,
 
 int pg_threshold_search(pg_context *ctx, int64_t n, const double *E,
                         const uint8_t *A_rel, double v_tot, double e_tot,
-                        double e_it, double rel_tol, int memory_pressure,
+                        double e_it, double rel_tol, int relax,
                         uint8_t *A_out, int *ok, double *t, int *trials) {
     if (!ctx) return PG_EINVAL;
     int rc = validate_list(ctx, n, n);
@@ -785,7 +802,7 @@ int pg_threshold_search(pg_context *ctx, int64_t n, const double *E,
                                         ctx->part, ctx->off, ctx->dtot));
     SearchOut so;
     rc = search(ctx, n, E, A_rel, v_tot, e_tot, e_it, rel_tol,
-                memory_pressure, nullptr, &so);
+                relax ? 1 : 0, nullptr, &so);
     if (rc) return rc;
     *ok = so.ok;
     *t = so.ok ? so.t : NAN;
@@ -871,8 +888,7 @@ int pg_integrate(pg_context *ctx, const pg_integrand *f, const double *lo,
         return fail(ctx, PG_EINVAL, "no positive tolerance");
     if (o.init_splits < 1) return fail(ctx, PG_EINVAL, "init_splits < 1");
     if (o.max_iters < 1) return fail(ctx, PG_EINVAL, "max_iters < 1");
-    if (o.error_rule != PG_ERR_RAW && o.error_rule != PG_ERR_NULL4)
-        return fail(ctx, PG_EINVAL, "unknown error rule %d", o.error_rule);
+    if (int rc_rules = check_rules(ctx, o)) return rc_rules;
     const int64_t cap = o.max_regions > 0 ? o.max_regions : ctx->cap;
     if (cap > ctx->cap)
         return fail(ctx, PG_ENOMEM, "max_regions %lld above the capacity %lld",
@@ -898,10 +914,11 @@ int pg_integrate(pg_context *ctx, const pg_integrand *f, const double *lo,
         if (!tr) return fail(ctx, PG_EINVAL, "cannot open %s", o.trace_path);
         const char magic[8] = {'P', 'G', 'T', 'R', 'A', 'C', 'E', '1'};
         const int32_t hd[2] = {d, f->family};
-        const int64_t zero[2] = {0, 0};
+        // the run's rules, which a replay must share
+        const int64_t rules[2] = {o.pmax_relax, o.error_rule};
         std::fwrite(magic, 1, 8, tr);
         std::fwrite(hd, 4, 2, tr);
-        std::fwrite(zero, 8, 2, tr);
+        std::fwrite(rules, 8, 2, tr);
     }
     // timing events: 5 per iteration (level 1 records only the two around
     // EVALUATE, level 2 all five)
@@ -1005,7 +1022,7 @@ int pg_integrate(pg_context *ctx, const pg_integrand *f, const double *lo,
                 Totals T2;
                 const CountReq cr{paired, ctx->V, &T2};
                 RUN_RC(search(ctx, n, ctx->E, ctx->A, v_tot, e_tot, e, tau,
-                              trig_b ? 1 : 0, &cr, &so));
+                              relax_pmax(o, trig_b), &cr, &so));
                 res.threshold_trials += so.trials;
                 rec.thr_ok = so.ok;
                 rec.thr_trials = so.trials;
@@ -1152,8 +1169,7 @@ static int run_batch(pg_context *ctx, int family, int dim, int B,
             return fail(ctx, PG_EINVAL, "empty or infinite range on axis %d", k);
     if (o.init_splits < 1 || o.max_iters < 1)
         return fail(ctx, PG_EINVAL, "init_splits / max_iters < 1");
-    if (o.error_rule != PG_ERR_RAW && o.error_rule != PG_ERR_NULL4)
-        return fail(ctx, PG_EINVAL, "unknown error rule %d", o.error_rule);
+    if (int rc_rules = check_rules(ctx, o)) return rc_rules;
     const int64_t cap = o.max_regions > 0 ? o.max_regions : ctx->cap;
     if (cap > ctx->cap)
         return fail(ctx, PG_ENOMEM, "max_regions %lld above the capacity %lld",
@@ -1360,7 +1376,7 @@ static int run_batch(pg_context *ctx, int family, int dim, int B,
                 z.n = S.n;
                 z.e_it = T.e;
                 z.allowance = T.e - (S.e_tot - tau * std::fabs(S.v_tot));
-                z.mem = trig_b ? 1 : 0;
+                z.relax = relax_pmax(o, trig_b);
                 z.mn = T.emin;
                 z.mx = T.emax;
                 z.t = T.e / (double)S.n;

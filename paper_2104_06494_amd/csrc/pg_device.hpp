@@ -264,9 +264,12 @@ __device__ inline void build_tree(const SearchState &S, double *thr) {
 
 // One trial of Algorithm 3 at threshold tt, given whether the memory and the
 // accuracy requirements hold there: accept, or move t (raise it when memory
-// fails, lower it when accuracy fails), counting direction changes (P_max
-// grows by 0.10 at each under memory pressure). Returns 1 when the search
-// has ended. The caller checks the trial limit first.
+// fails, lower it when accuracy fails), counting direction changes. With
+// st.relax set, P_max grows by 0.10 at each direction change, up to 0.95
+// (Section 3.5.3); the host sets it for every search, or (the memory-only
+// option) only for searches run because the list would overflow its cap.
+// Returns 1 when the search has ended. The caller checks the trial limit
+// first.
 __device__ inline int search_step(SearchState &st, double tt, bool mem_ok,
                                   bool acc_ok) {
     ++st.trials;
@@ -284,7 +287,7 @@ __device__ inline int search_step(SearchState &st, double tt, bool mem_ok,
     }
     if (st.last_dir != 0 && dir != st.last_dir) {
         ++st.dir_changes;
-        if (st.mem) st.P_max = fmin(st.P_max + 0.10, 0.95);
+        if (st.relax) st.P_max = fmin(st.P_max + 0.10, 0.95);
         if (st.dir_changes >= THR_MAX_DIRCHG) { st.done = 1; return 1; }
     }
     st.last_dir = dir;

@@ -81,7 +81,7 @@ struct SearchState {
     double t;             // next threshold to try (root of the next pass)
     double P_max;
     double t_acc;         // accepted threshold
-    int mem;              // searching under memory pressure
+    int relax;            // P_max grows at each direction change
     int last_dir, dir_changes, trials;
     int done, ok;
 };
@@ -248,7 +248,7 @@ hipError_t launch_reduce_scan(hipStream_t st, int64_t nseg, SegPartials part,
 hipError_t launch_search_hist(hipStream_t st, int64_t n, const double *E,
                               const uint8_t *A_rel, SearchState *S,
                               uint32_t *cnt, unsigned long long *sum,
-                              double e_it, double allowance, int mem,
+                              double e_it, double allowance, int relax,
                               const Totals *minmax);
 // One pass (TRIAL_DEPTH trials) of the search: k_trials + k_trial_walk; a
 // no-op once the search has ended. blk_part holds 2 TRIAL_M x TRIAL_BLOCKS

@@ -75,13 +75,13 @@ k_reduce_scan(int64_t nseg, SegPartials part, uint32_t *__restrict__ offsets,
 // The state a search starts from (Algorithm 3): first threshold e_it / n,
 // P_max = 0.25, min / max E from the totals of the pass before it.
 __device__ inline SearchState search_start(int64_t n, double e_it,
-                                           double allowance, int mem,
+                                           double allowance, int relax,
                                            const Totals &minmax) {
     SearchState s{};
     s.n = n;
     s.e_it = e_it;
     s.allowance = allowance;
-    s.mem = mem;
+    s.relax = relax;
     s.mn = minmax.emin;
     s.mx = minmax.emax;
     s.t = e_it / (double)n;
@@ -91,10 +91,10 @@ __device__ inline SearchState search_start(int64_t n, double e_it,
 }
 
 __global__ void k_search_init(SearchState *__restrict__ S, int64_t n,
-                              double e_it, double allowance, int mem,
+                              double e_it, double allowance, int relax,
                               const Totals *__restrict__ minmax) {
     if (threadIdx.x != 0) return;
-    *S = search_start(n, e_it, allowance, mem, *minmax);
+    *S = search_start(n, e_it, allowance, relax, *minmax);
 }
 
 // Regions per histogram block for a list of more than 256 segments: about
@@ -126,8 +126,8 @@ k_hist(int64_t n, const double *__restrict__ E,
 __global__ void __launch_bounds__(HIST_THREADS)
 k_hist_walk(SearchState *__restrict__ S, uint32_t *__restrict__ cnt,
             unsigned long long *__restrict__ sum, int64_t n, double e_it,
-            double allowance, int mem, const Totals *__restrict__ minmax) {
-    const SearchState init = search_start(n, e_it, allowance, mem, *minmax);
+            double allowance, int relax, const Totals *__restrict__ minmax) {
+    const SearchState init = search_start(n, e_it, allowance, relax, *minmax);
     hist_walk(init, S, cnt, sum);
 }
 
@@ -308,11 +308,11 @@ hipError_t launch_reduce_scan(hipStream_t st, int64_t nseg, SegPartials part,
 hipError_t launch_search_hist(hipStream_t st, int64_t n, const double *E,
                               const uint8_t *A_rel, SearchState *S,
                               uint32_t *cnt, unsigned long long *sum,
-                              double e_it, double allowance, int mem,
+                              double e_it, double allowance, int relax,
                               const Totals *minmax) {
     if (n <= 0) {
         hipLaunchKernelGGL(k_search_init, dim3(1), dim3(64), 0, st, S, n,
-                           e_it, allowance, mem, minmax);
+                           e_it, allowance, relax, minmax);
         return hipGetLastError();
     }
     const int64_t nseg = seg_count(n, 0);
@@ -323,7 +323,7 @@ hipError_t launch_search_hist(hipStream_t st, int64_t n, const double *E,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_hist_walk, dim3(1), dim3(HIST_THREADS), 0, st, S, cnt,
-                       sum, n, e_it, allowance, mem, minmax);
+                       sum, n, e_it, allowance, relax, minmax);
     return hipGetLastError();
 }
 

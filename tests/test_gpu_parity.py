@@ -13,7 +13,7 @@ import oracle
 import workloads as W
 from workloads import closed_forms as cf
 
-from parity import assert_region_parity, rel_close
+from parity import assert_region_parity, check_free_run, rel_close
 
 pytestmark = pytest.mark.gpu
 
@@ -219,9 +219,9 @@ def test_classify_parity(ctx, n, paired):
     assert sums[4:] == ref[4:]
 
 
-@pytest.mark.parametrize("seed,mem", [(0, 0), (1, 1), (2, 0), (3, 1), (4, 0)])
-def test_threshold_search_parity(ctx, seed, mem):
-    _say("threshold", seed, mem)
+@pytest.mark.parametrize("seed,relax", [(0, 0), (1, 1), (2, 0), (3, 1), (4, 0)])
+def test_threshold_search_parity(ctx, seed, relax):
+    _say("threshold", seed, relax)
     rng = np.random.default_rng(seed)
     n = int(rng.integers(1000, 60000))
     E = rng.lognormal(sigma=2.5, size=n) * 1e-9
@@ -243,17 +243,17 @@ def test_threshold_search_parity(ctx, seed, mem):
         np.testing.assert_array_equal(A.cpu().numpy(), A_rel)
 
 
-THRESH_SPREAD = [(seed, mem, sigma) for seed in (11, 12, 13) for mem in (0, 1)
+THRESH_SPREAD = [(seed, relax, sigma) for seed in (11, 12, 13) for relax in (0, 1)
                  for sigma in (0.2, 1.0, 5.0)]
 
 
-@pytest.mark.parametrize("seed,mem,sigma", THRESH_SPREAD)
-def test_threshold_search_spread(ctx, seed, mem, sigma):
+@pytest.mark.parametrize("seed,relax,sigma", THRESH_SPREAD)
+def test_threshold_search_spread(ctx, seed, relax, sigma):
     """Narrow and wide error spreads: many regions share a histogram bin
     (undecided trials, exact passes) or the search runs long (direction
     changes, P_max growth, its limits)."""
-    _say("threshold-spread", seed, mem, sigma)
-    rng = np.random.default_rng(seed * 7 + mem)
+    _say("threshold-spread", seed, relax, sigma)
+    rng = np.random.default_rng(seed * 7 + relax)
     n = int(rng.integers(3000, 200000))
     v = 1.8e-5
     tau = float(10.0 ** rng.uniform(-8, -3))
@@ -336,29 +336,38 @@ REPLAY = [
 ]
 
 
+PMAX = ["paper", "memory"]
+
+
+@pytest.mark.parametrize("pmax", PMAX)
 @pytest.mark.parametrize("name,mk,kw", REPLAY, ids=[c[0] for c in REPLAY])
-def test_integrate_replay(ctx, tmp_path, name, mk, kw):
-    _say("replay", name)
+def test_integrate_replay(ctx, tmp_path, name, mk, kw, pmax):
+    _say("replay", name, pmax)
     wl = mk()
-    r, o = _replay(ctx, wl, tmp_path, **kw)
+    r, o = _replay(ctx, wl, tmp_path, pmax_relax=pmax, **kw)
     _assert_replay(r, o)
-    if r.status_name == "OK":
+    sign_changing = wl.family == "oscillatory" and wl.relerr_filter
+    if r.status_name in ("OK", "NO_ACTIVE") and not sign_changing:
         exact = cf.exact(wl.family, wl.params, wl.d)
         tau = kw.get("rel_tol", wl.rel_tol)
-        assert abs(r.estimate - exact) <= tau * abs(exact)
-        assert r.error <= tau * abs(r.estimate)
+        check_free_run(r, exact, tau, allow_no_active=pmax == "paper")
 
 
-def test_headline_workload_replay(ctx, tmp_path):
+@pytest.mark.parametrize("pmax", PMAX)
+def test_headline_workload_replay(ctx, tmp_path, pmax):
     """d=5 Gaussian to 1e-6 with the 2^21-region cap: replay parity, the
-    closed form met, the memory trigger fired (the list reached the cap)."""
-    _say("replay-headline")
+    closed form met, the memory trigger fired (the list reached the cap).
+    Under the P_max rule of Section 3.5.3 the run ends with every region
+    finished and the summed error just above the tolerance (NO_ACTIVE), the
+    estimate still within it; under the memory-only rule it converges."""
+    _say("replay-headline", pmax)
     wl = W.gaussian_d5()
-    r, o = _replay(ctx, wl, tmp_path)
+    r, o = _replay(ctx, wl, tmp_path, pmax_relax=pmax)
     _assert_replay(r, o)
     exact = cf.exact(wl.family, wl.params, wl.d)
-    assert r.status_name == "OK"
-    assert abs(r.estimate - exact) <= wl.rel_tol * abs(exact)
+    check_free_run(r, exact, wl.rel_tol, allow_no_active=pmax == "paper")
+    if pmax == "memory":
+        assert r.status_name == "OK"
     assert r.peak_regions == wl.max_regions
 
 

@@ -158,7 +158,7 @@ def test_monomial_has_no_gradient():
 
 
 @pytest.mark.parametrize("kw,status", [
-    (dict(rel_tol=1e-7), "OK"),
+    (dict(rel_tol=1e-7, pmax_relax="memory"), "OK"),
     (dict(rel_tol=1e-9, max_iters=3), "MAX_ITERS"),
     (dict(rel_tol=1e-9, max_regions=600, threshold_filter=0), "MEMORY_EXHAUSTED"),
 ])
@@ -187,7 +187,8 @@ def test_run_leaves_add_up_when_no_region_stays_active():
 def test_corner_peak_run_gradient_against_closed_form():
     d = 5
     p = np.array([0.4, 1.1, 1.7, 0.9, 0.25])
-    r = oracle.integrate("corner_peak", d, p, rel_tol=1e-8, init_splits=2, grad=True)
+    r = oracle.integrate("corner_peak", d, p, rel_tol=1e-8, init_splits=2, grad=True,
+                         pmax_relax="memory")
     assert r.status_name == "OK"
     ref = cf.corner_peak_grad(p, d)
     np.testing.assert_allclose(r.grad, ref, rtol=1e-6)

@@ -35,6 +35,7 @@ MUTANTS = {
                          "if (dir < 0) t = t + (mx - t) / 2.0;"),
     "search_budget": ("if (e_abar <= P_max * (e_it - e_b)) {",
                       "if (e_abar <= P_max * e_b) {"),
+    "search_pmax_step": ("P_max = P_max + 0.10;", "P_max = P_max + 0.05;"),
     "uniform_split_offset": ("lo[k * ld + r] = a[k] + (double)digit * width;",
                              "lo[k * ld + r] = a[k] + (double)(digit + 1) * width;"),
     "sum_uncompensated": ("    return s + c;\n}", "    return s;\n}"),
@@ -88,7 +89,27 @@ NULL4_MUTANTS = {
     "null_smallest_magnitude": ("return big > e1 ? big : e1;", "return big < e1 ? big : e1;"),
 }
 
+# mistakes in the replay mode's certification of ties (each would let a
+# real disagreement of a GPU run pass as a rounding tie) and in which
+# searches relax P_max, caught by the replay pins
+REPLAY_MUTANTS = {
+    "replay_axis_always_tie": ("if (cert) rs->axis_override++;",
+                               "if (1) rs->axis_override++;"),
+    "replay_class_always_tie": ("if (c_rel) rs->class_override++;",
+                                "if (1) rs->class_override++;"),
+    "replay_threshold_always_tie": ("else if (c_thr) rs->thr_override++;",
+                                    "else if (1) rs->thr_override++;"),
+    "replay_term_always_tie": ("int cert = gap <= 1e-9 * e_tot;", "int cert = 1;"),
+    "replay_trigger_always_tie": (
+        "int cert = gap <= 1e-9 * tau_rel * fabs(v_tot) && !trig_b;", "int cert = 1;"),
+    "replay_search_unchecked": (
+        "if (ok != (rec.thr_ok != 0) || trials != rec.thr_trials) {", "if (0) {"),
+    "run_pmax_memory_only": ("pmax_relax == 0 || 2 * n_rel > cap,",
+                             "2 * n_rel > cap,"),
+}
+
 CASES = [(n, "test_oracle_pins.py") for n in sorted(MUTANTS)] + \
+        [(n, "test_oracle_replay_pins.py") for n in sorted(REPLAY_MUTANTS)] + \
         [(n, "test_oracle_grad_pins.py") for n in sorted(GRAD_MUTANTS)] + \
         [(n, "test_oracle_suite_pins.py") for n in sorted(SUITE_MUTANTS)] + \
         [(n, "test_oracle_null4_pins.py") for n in sorted(NULL4_MUTANTS)]
@@ -96,7 +117,8 @@ CASES = [(n, "test_oracle_pins.py") for n in sorted(MUTANTS)] + \
 
 @pytest.mark.parametrize("name,pins", CASES, ids=[c[0] for c in CASES])
 def test_mutant_is_caught(name, pins, tmp_path):
-    old, new = {**MUTANTS, **GRAD_MUTANTS, **SUITE_MUTANTS, **NULL4_MUTANTS}[name]
+    old, new = {**MUTANTS, **GRAD_MUTANTS, **SUITE_MUTANTS, **NULL4_MUTANTS,
+                **REPLAY_MUTANTS}[name]
     src = open(SRC).read()
     assert src.count(old) == 1, f"mutation anchor not unique: {name}"
     mut = tmp_path / "mutant.c"

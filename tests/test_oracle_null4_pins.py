@@ -317,8 +317,12 @@ def test_more_reliable_than_the_raw_error_on_unresolved_peaks():
     ("box", 4, [7.5], 1e-6, 1),
 ])
 def test_oracle_runs_with_the_null_rules_meet_closed_forms(family, d, params, tol, relerr):
+    # converged runs need the memory-only P_max rule: with the rule of
+    # Section 3.5.3 some of these end with every region finished just above
+    # the tolerance (pinned in test_oracle_pins.py)
     r = oracle.integrate(family, d, params, rel_tol=tol, init_splits=2,
-                         relerr_filter=relerr, error_rule="null4")
+                         relerr_filter=relerr, error_rule="null4",
+                         pmax_relax="memory")
     assert r.status_name == "OK", r
     ex = cf.exact(family, params, d)
     assert abs(r.estimate - ex) <= tol * abs(ex)

@@ -20,6 +20,7 @@ import pytest
 
 import oracle
 import workloads as W
+from parity import check_free_run
 from workloads import closed_forms as cf
 
 
@@ -127,11 +128,14 @@ def test_discontinuous_aligned_grid_meets_the_closed_form():
     ("c0", 3, [10.0, 10.0, 10.0, 0.5, 0.5, 0.5], 1e-6, 2),
     ("discontinuous", 3, [5.0, 6.0, 7.0, 0.4, 0.5, 0.6], 1e-4, 2),
 ])
-def test_oracle_runs_meet_closed_forms(family, d, params, tol, g):
-    r = oracle.integrate(family, d, params, rel_tol=tol, init_splits=g)
-    assert r.status_name == "OK", r
+@pytest.mark.parametrize("pmax", ["paper", "memory"])
+def test_oracle_runs_meet_closed_forms(family, d, params, tol, g, pmax):
+    r = oracle.integrate(family, d, params, rel_tol=tol, init_splits=g,
+                         pmax_relax=pmax)
     ex = cf.exact(family, params, d)
-    assert abs(r.estimate - ex) <= tol * abs(ex)
+    # the memory-only P_max rule converges; the paper's may end NO_ACTIVE
+    # just above the tolerance with the estimate still within it
+    check_free_run(r, ex, tol, allow_no_active=pmax == "paper")
 
 
 def test_paper_suite_definitions():
