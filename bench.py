@@ -12,8 +12,14 @@ Prints one JSON line:
               (sum of regions evaluated x 93 points / wall time)
   roofline    the EVALUATE kernel (the method's arithmetic) against MI355X's
               FP64 vector peak, from HIP events recorded on its stream
-  cpu_baseline  the CPU oracle (single thread) on a bounded sample of the
-              same workload: the first 12 iterations of the same run
+  cpu_baseline  the CPU oracle on the same run to convergence: its parity
+              build on one core and its OpenMP build on all the host's
+              cores, with the host's CPU model and count
+  configs     the product-peak (d=3) and oscillatory (d=8, relative-error
+              filter on and off) workloads; headline_other_rules: the
+              headline under the other threshold-search rules
+  batched, adjoint  many integrals in one run against single runs, and
+              the forward run with and without dI/dtheta (medians)
 
 Other modes feed the profiles: --mode integrand (integrand values only, to
 count one evaluation's FP64 operations with rocprofv3 counters) and
@@ -32,11 +38,11 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# FP64 operations of one Gaussian evaluation in 5 dimensions, counted with
-# rocprofv3 ((ADD + MUL + TRANS + 2 FMA)_F64 per evaluation) on the
-# integrand-only kernel; see profiles/evaluate_gaussian_d5_counters.txt.
-# Algorithmic FLOP per region = 93 points x (F + 1 orbit accumulation).
-F_GAUSSIAN_D5 = 47.0
+# FP64 operations of one evaluation of an integrand, counted with rocprofv3
+# ((ADD + MUL + TRANS + 2 FMA)_F64 per evaluation) on the integrand-only
+# kernel (--mode integrand); see profiles/evaluate_gaussian_d5_counters.txt.
+# Algorithmic FLOP per region = N points x (F + 1 orbit accumulation).
+F_FLOP = {("gaussian", 5): 47.0}
 # HBM bytes per evaluate launch of this workload from FETCH_SIZE / WRITE_SIZE
 # (scaled by a plain copy), valid only for the kernel source they were taken
 # on (first 16 hex digits of the sha256 of pg_eval_kernels.hpp followed by
@@ -63,6 +69,92 @@ def _kernel_sha():
     return h.hexdigest()[:16]
 
 
+def _host():
+    """The host the CPU figures come from: CPU model, logical CPUs, and the
+    CPUs this process may run on."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "cpus_available": len(os.sched_getaffinity(0)),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def _flop_per_eval(family, d):
+    return F_FLOP.get((family, d))
+
+
+def timed_runs(ctx, wl, steps, warmup, **kw):
+    """`steps` whole integrations of `wl` after `warmup` untimed ones, each
+    timed on the host (pg_integrate blocks until the result is known) with
+    HIP events around its EVALUATE launches; then one more run with events
+    around every phase. Returns the first timed run's result, the per-step
+    wall times and the evaluate-kernel figures."""
+    import torch
+    for _ in range(warmup):
+        ctx.integrate_workload(wl, timing=1, **kw)
+    torch.cuda.synchronize()
+    results, step_s = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        # HIP events around the EVALUATE launches only (the roofline's
+        # duration); a full phase breakdown would add 3 events an iteration
+        r = ctx.integrate_workload(wl, timing=1, **kw)
+        step_s.append(time.perf_counter() - ts)
+        results.append(r)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # the phase breakdown, from one more run outside the timed region
+    rp = ctx.integrate_workload(wl, timing=2, **kw)
+    r0 = results[0]
+    eval_ms = sum(r.phase_ms[0] for r in results)
+    launches = sum(r.eval_launches for r in results)
+    regions = sum(r.regions_evaluated for r in results)
+    npts = wl.npoints
+    out = {"result": r0, "wall_s": wall, "step_s": step_s,
+           "fevals": sum(r.fevals for r in results),
+           "eval_ms": eval_ms, "launches": launches, "regions": regions,
+           "phases": list(rp.phase_ms)}
+    F = _flop_per_eval(wl.family, wl.d)
+    out["alg_flop"] = regions * npts * (F + 1.0) if F is not None else None
+    return out
+
+
+def _run_summary(wl, T, exact):
+    """One workload's figures: time-to-tol (median and range over the timed
+    runs), evaluations per second over the whole runs and over the EVALUATE
+    launches, the evaluate kernel against the FP64 vector peak, the phases
+    of one run, and the result against the closed form."""
+    r = T["result"]
+    out = {"time_to_tol_ms": 1e3 * statistics.median(T["step_s"]),
+           "time_to_tol_ms_min": 1e3 * min(T["step_s"]),
+           "time_to_tol_ms_max": 1e3 * max(T["step_s"]),
+           "runs": len(T["step_s"]),
+           "evals_per_s": T["fevals"] / T["wall_s"],
+           "eval_evals_per_s": T["regions"] * wl.npoints / (T["eval_ms"] * 1e-3),
+           "status": r.status_name, "estimate": r.estimate, "error": r.error,
+           "true_rel_err": abs(r.estimate - exact) / abs(exact),
+           "est_rel_err": r.error / abs(r.estimate),
+           "iterations": r.iterations, "regions_evaluated": r.regions_evaluated,
+           "peak_regions": r.peak_regions, "threshold_calls": r.threshold_calls,
+           "threshold_trials": r.threshold_trials,
+           "eval_launches_per_run": T["launches"] / len(T["step_s"]),
+           "phase_ms_one_run": dict(zip(("evaluate", "post_process",
+                                         "threshold_and_host", "filter_split"),
+                                        T["phases"]))}
+    if T["alg_flop"] is not None:
+        achieved = T["alg_flop"] / (T["eval_ms"] * 1e-3) / 1e12
+        out["evaluate_tflops"] = achieved
+        out["evaluate_frac_fp64_peak"] = achieved / PEAK_FP64_TFLOPS
+    return out
+
+
 def headline(args):
     import torch
     import paper_2104_06494_amd as pg
@@ -72,34 +164,25 @@ def headline(args):
     wl = W.gaussian_d5()
     npts = wl.npoints
     torch.cuda.set_device(0)
-    ctx = pg.Context(capacity=wl.max_regions, dim_max=wl.d)
-    for _ in range(args.warmup):
-        ctx.integrate_workload(wl, timing=1)
-    torch.cuda.synchronize()
-    results, step_s = [], []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        # HIP events around the EVALUATE launches only (the roofline's
-        # duration); a full phase breakdown would add 3 events an iteration
-        r = ctx.integrate_workload(wl, timing=1)
-        step_s.append(time.perf_counter() - ts)
-        results.append(r)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    # the phase breakdown, from one more run outside the timed region
-    rp = ctx.integrate_workload(wl, timing=2)
-
-    fevals = sum(r.fevals for r in results)
-    value = fevals / wall
-    r0 = results[0]
     exact = cf.exact(wl.family, wl.params, wl.d)
-    eval_ms = sum(r.phase_ms[0] for r in results)
-    launches = sum(r.eval_launches for r in results)
-    regions = sum(r.regions_evaluated for r in results)
-    alg_flop = regions * npts * (F_GAUSSIAN_D5 + 1.0)
-    achieved = alg_flop / (eval_ms * 1e-3) / 1e12
-    phases = list(rp.phase_ms)
+    with pg.Context(capacity=wl.max_regions, dim_max=wl.d) as ctx:
+        T = timed_runs(ctx, wl, args.steps, args.warmup)
+        # the same workload under the other threshold-search rules (the P_max
+        # rule of Section 3.5.3 without a reserve for the active regions, and
+        # the memory-only P_max rule, a departure from that section)
+        rules = {}
+        if not args.no_configs:
+            for name, kw in (("paper_pmax_listing_budget",
+                              dict(pmax_relax="paper", budget="listing")),
+                             ("memory_only_pmax_reserve_budget",
+                              dict(pmax_relax="memory", budget="reserve"))):
+                rules[name] = _run_summary(wl, timed_runs(ctx, wl, 5, 1, **kw), exact)
+
+    r0 = T["result"]
+    value = T["fevals"] / T["wall_s"]
+    launches = T["launches"]
+    achieved = T["alg_flop"] / (T["eval_ms"] * 1e-3) / 1e12
+    summ = _run_summary(wl, T, exact)
     out = {
         "metric": "FP64 integrand evals/s + time-to-tol at 1e-6; batched & adjoint vs plain, 1 GPU",
         "value": value,
@@ -107,7 +190,7 @@ def headline(args):
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * wall / args.steps,
+        "ms_per_step": 1e3 * T["wall_s"] / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -116,16 +199,14 @@ def headline(args):
         "config": {"workload": "gaussian_d5_tol1e-6", "family": "gaussian", "d": 5,
                    "rel_tol": wl.rel_tol, "init_grid": "4^5",
                    "max_regions": wl.max_regions, "points_per_region": npts,
-                   "seed": 2},
-        "time_to_tol_ms": 1e3 * statistics.median(step_s),
-        "result": {"status": r0.status_name, "estimate": r0.estimate,
-                   "error": r0.error, "true_rel_err": abs(r0.estimate - exact) / abs(exact),
-                   "iterations": r0.iterations, "regions_evaluated": r0.regions_evaluated,
-                   "peak_regions": r0.peak_regions, "fevals": r0.fevals,
-                   "threshold_calls": r0.threshold_calls,
-                   "threshold_trials": r0.threshold_trials},
-        "phase_ms_one_run": {"evaluate": phases[0], "post_process": phases[1],
-                             "threshold_and_host": phases[2], "filter_split": phases[3],
+                   "seed": 2, "pmax_relax": "paper", "budget": "reserve",
+                   "error_rule": "raw"},
+        "time_to_tol_ms": summ["time_to_tol_ms"],
+        "result": {k: summ[k] for k in ("status", "estimate", "error", "true_rel_err",
+                                        "iterations", "regions_evaluated",
+                                        "peak_regions", "threshold_calls",
+                                        "threshold_trials")},
+        "phase_ms_one_run": {**summ["phase_ms_one_run"],
                              "note": "one run after the timed steps, 5 HIP events an iteration"},
         "roofline": {
             "kernel": "k_evaluate<gaussian,5>",
@@ -137,11 +218,15 @@ def headline(args):
             "traffic": (EVAL_TRAFFIC["bytes_per_launch"]
                         if _kernel_sha() == EVAL_TRAFFIC["kernel_sha256"] else None),
             "traffic_unit": "HBM bytes per launch",
-            "avg_launch_ms": eval_ms / launches,
-            "alg_flop_per_launch": alg_flop / launches,
-            "eval_evals_per_s": regions * npts / (eval_ms * 1e-3),
+            "avg_launch_ms": T["eval_ms"] / launches,
+            "alg_flop_per_launch": T["alg_flop"] / launches,
+            "eval_evals_per_s": summ["eval_evals_per_s"],
         },
     }
+    if rules:
+        out["headline_other_rules"] = rules
+    if not args.no_configs:
+        out["configs"] = other_configs(args)
     if not args.no_batched:
         out["batched"] = batched(args)
     if not args.no_adjoint:
@@ -151,12 +236,47 @@ def headline(args):
     print(json.dumps(out), flush=True)
 
 
+def other_configs(args):
+    """The small product peak (d=3 to 1e-3, 4^3 grid) and the oscillatory
+    integrand (d=8 to 1e-5, 2^8 grid, with the relative-error filter on and
+    off): median time-to-tol over 7 runs after 2 warm-up runs, evaluations
+    per second, the evaluate kernel's fraction of the FP64 peak, phases."""
+    import torch
+    import paper_2104_06494_amd as pg
+    import workloads as W
+    from workloads import closed_forms as cf
+
+    out = {}
+    for name, wl in (("product_peak_d3_tol1e-3", W.product_peak_d3()),
+                     ("oscillatory_d8_tol1e-5_relerr_on", W.oscillatory_d8(1)),
+                     ("oscillatory_d8_tol1e-5_relerr_off", W.oscillatory_d8(0))):
+        exact = cf.exact(wl.family, wl.params, wl.d)
+        with pg.Context(capacity=wl.max_regions, dim_max=wl.d) as ctx:
+            out[name] = _run_summary(wl, timed_runs(ctx, wl, 7, 2), exact)
+        torch.cuda.empty_cache()
+    return out
+
+
+def _median_runs(fn, reps):
+    """fn() `reps` times, each bracketed by device synchronisations; returns
+    (last result, median seconds, all seconds)."""
+    import torch
+    ts, res = [], None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return res, statistics.median(ts), ts
+
+
 def batched(args):
     """The 1024 d=6 corner-peak integrals (per-integral a ~ U[0,2]^6 and
     rel_tol 10^U[-7,-4], seed 4, 2^6 initial grid, 2^21-region cap each)
     as one batched run and as 1024 single runs one after another, on the
-    same context. Both give the same results; evals/s and wall time of
-    each (one untimed warm-up of the batched run first)."""
+    same context (median of --reps runs each, after one warm-up of the
+    batched run). Both give the same results."""
     import torch
     import paper_2104_06494_amd as pg
     import workloads as W
@@ -165,96 +285,112 @@ def batched(args):
     wl = W.corner_peak_batch_d6()
     B = min(wl.B, args.batch_count) if args.batch_count else wl.B
     slots = args.batch_slots
-    ctx = pg.Context(capacity=slots * wl.max_regions, dim_max=wl.d)
-    ctx.integrate_batch_workload(wl, count=min(B, 2 * slots))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rb = ctx.integrate_batch_workload(wl, count=B)
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
-    fe = sum(r.fevals for r in rb)
-    met = 0
-    for b, r in enumerate(rb):
-        exact = cf.exact(wl.family, wl.params[b], wl.d)
-        met += abs(r.estimate - exact) <= wl.rel_tol[b] * abs(exact)
-    out = {"workload": "corner_peak_batch_d6", "B": B, "slots_in_flight": slots,
-           "evals_per_s": fe / tb, "wall_ms": 1e3 * tb, "fevals": fe,
-           "status_ok": sum(r.status_name == "OK" for r in rb),
-           "closed_form_met": int(met),
-           "regions_evaluated": sum(r.regions_evaluated for r in rb),
-           "max_iterations": max(r.iterations for r in rb)}
-    if not args.no_plain:
-        t0 = time.perf_counter()
-        rp = [ctx.integrate_workload(wl.instance(b)) for b in range(B)]
-        torch.cuda.synchronize()
-        tp = time.perf_counter() - t0
-        out["plain_sequential"] = {"evals_per_s": fe / tp, "wall_ms": 1e3 * tp}
-        out["speedup_vs_plain"] = tp / tb
-        out["same_schedule_as_plain"] = sum(
-            (a.status, a.iterations, a.regions_evaluated) ==
-            (b.status, b.iterations, b.regions_evaluated) for a, b in zip(rb, rp))
-    ctx.close()
+    with pg.Context(capacity=slots * wl.max_regions, dim_max=wl.d) as ctx:
+        ctx.integrate_batch_workload(wl, count=min(B, 2 * slots))
+        rb, tb, tbs = _median_runs(lambda: ctx.integrate_batch_workload(wl, count=B),
+                                   args.reps)
+        fe = sum(r.fevals for r in rb)
+        met = 0
+        for b, r in enumerate(rb):
+            exact = cf.exact(wl.family, wl.params[b], wl.d)
+            met += abs(r.estimate - exact) <= wl.rel_tol[b] * abs(exact)
+        out = {"workload": "corner_peak_batch_d6", "B": B, "slots_in_flight": slots,
+               "evals_per_s": fe / tb, "wall_ms": 1e3 * tb,
+               "wall_ms_runs": [1e3 * t for t in tbs], "fevals": fe,
+               "status_ok": sum(r.status_name == "OK" for r in rb),
+               "closed_form_met": int(met),
+               "regions_evaluated": sum(r.regions_evaluated for r in rb),
+               "max_iterations": max(r.iterations for r in rb)}
+        if not args.no_plain:
+            rp, tp, tps = _median_runs(
+                lambda: [ctx.integrate_workload(wl.instance(b)) for b in range(B)],
+                args.reps)
+            out["plain_sequential"] = {"evals_per_s": fe / tp, "wall_ms": 1e3 * tp,
+                                       "wall_ms_runs": [1e3 * t for t in tps]}
+            out["speedup_vs_plain"] = tp / tb
+            out["same_schedule_as_plain"] = sum(
+                (a.status, a.iterations, a.regions_evaluated) ==
+                (b.status, b.iterations, b.regions_evaluated) for a, b in zip(rb, rp))
     torch.cuda.empty_cache()
     return out
 
 
+def _grad_scaled_error(G, ref, I, params, d):
+    """Largest |dI/dtheta - closed form| over the parameters, in units of
+    tau-free scale |ref_k| + |I| / s_k, s_k the parameter's natural scale
+    (a_k for a width parameter a_k, the Gaussian's width 1 / a_k for a
+    centre u_k): the run bounds the estimate's error by tau |I|, and on a
+    fixed partition that error moves by about itself when a parameter moves
+    by its scale."""
+    import numpy as np
+    a = np.abs(np.asarray(params[:d]))
+    scale = np.concatenate([a, 1.0 / a])
+    return float(np.max(np.abs(G - ref) / (np.abs(ref) + abs(I) / scale)))
+
+
 def adjoint(args):
-    """The 256 d=6 Gaussian parameter points (a ~ U[5,20]^6, u ~ U[0.2,0.8]^6,
-    seed 5, rel_tol 1e-5, 2^6 initial grid, 2^22-region cap each), batched:
-    forward only, then forward plus the derivative over each final
-    partition (same decisions, so the same regions); and the forward as 256
-    single runs. Also how many estimates and gradients meet the closed form."""
+    """Gaussian parameter points, d=6 (a ~ U[5,20]^6, u ~ U[0.2,0.8]^6, seed
+    5, 2^6 initial grid), batched: forward only, then forward plus the
+    derivative over each final partition (same decisions, so the same
+    regions), medians of --reps runs; and the forward as single runs. Also
+    how many estimates meet the closed form and how far the gradients are
+    from theirs (relative to the tolerance, on the scale of
+    _grad_scaled_error)."""
     import numpy as np
     import torch
     import paper_2104_06494_amd as pg
     import workloads as W
     from workloads import closed_forms as cf
 
-    wl = W.gaussian_grad_d6()
-    B = min(wl.B, args.batch_count) if args.batch_count else wl.B
-    slots = max(1, args.batch_slots // 2)
-    ctx = pg.Context(capacity=slots * wl.max_regions, dim_max=wl.d)
-    ctx.integrate_batch_workload(wl, count=min(B, slots), grad=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rf = ctx.integrate_batch_workload(wl, count=B)
-    torch.cuda.synchronize()
-    tf = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    rg, G, _ = ctx.integrate_batch_workload(wl, count=B, grad=True)
-    torch.cuda.synchronize()
-    tg = time.perf_counter() - t0
-    fe = sum(r.fevals for r in rf)
-    same = sum((a.status, a.regions_evaluated, a.estimate) ==
-               (b.status, b.regions_evaluated, b.estimate) for a, b in zip(rf, rg))
-    est_ok = grad_ok = 0
-    gerr = []
-    for b in range(B):
-        I, dA, dU = cf.gaussian_grad(wl.params[b], wl.d)
-        ref = np.concatenate([dA, dU])
-        tau = wl.rel_tol[b]
-        est_ok += abs(rg[b].estimate - I) <= tau * abs(I)
-        e = float(np.max(np.abs(G[b] - ref)) / np.max(np.abs(ref)))
-        gerr.append(e)
-        grad_ok += e <= 100 * tau
-    out = {"workload": "gaussian_grad_d6", "B": B, "slots_in_flight": slots,
-           "rel_tol": float(wl.rel_tol[0]),
-           "forward": {"evals_per_s": fe / tf, "wall_ms": 1e3 * tf},
-           "forward_adjoint": {"evals_per_s": fe / tg, "wall_ms": 1e3 * tg},
-           "adjoint_overhead": tg / tf - 1.0, "fevals": fe,
-           "same_run_with_adjoint": same,
-           "status_ok": sum(r.status_name == "OK" for r in rg),
-           "estimate_meets_closed_form": int(est_ok),
-           "gradient_within_100tau_of_closed_form": int(grad_ok),
-           "median_gradient_rel_err": float(np.median(gerr))}
-    if not args.no_plain:
-        t0 = time.perf_counter()
+    wl = W.gaussian_grad_d6(rel_tol=args.adjoint_tol)
+    if args.adjoint_cap:
+        wl.max_regions = args.adjoint_cap
+    B = min(wl.B, args.adjoint_count) if args.adjoint_count else wl.B
+    slots = max(1, min(args.batch_slots // 2, (1 << 27) // wl.max_regions))
+    kw = dict(error_rule=args.adjoint_error_rule)
+    with pg.Context(capacity=slots * wl.max_regions, dim_max=wl.d) as ctx:
+        ctx.integrate_batch_workload(wl, count=min(B, slots), grad=True, **kw)
+        rf, tf, tfs = _median_runs(
+            lambda: ctx.integrate_batch_workload(wl, count=B, **kw), args.reps)
+        (rg, G, _), tg, tgs = _median_runs(
+            lambda: ctx.integrate_batch_workload(wl, count=B, grad=True, **kw),
+            args.reps)
+        fe = sum(r.fevals for r in rf)
+        same = sum((a.status, a.regions_evaluated, a.estimate) ==
+                   (b.status, b.regions_evaluated, b.estimate) for a, b in zip(rf, rg))
+        est_ok, gerr = 0, []
         for b in range(B):
-            ctx.integrate_workload(wl.instance(b))
-        torch.cuda.synchronize()
-        tp = time.perf_counter() - t0
-        out["plain_sequential"] = {"evals_per_s": fe / tp, "wall_ms": 1e3 * tp}
-    ctx.close()
+            I, dA, dU = cf.gaussian_grad(wl.params[b], wl.d)
+            ref = np.concatenate([dA, dU])
+            tau = wl.rel_tol[b]
+            est_ok += abs(rg[b].estimate - I) <= tau * abs(I)
+            gerr.append(_grad_scaled_error(G[b], ref, I, wl.params[b], wl.d) / tau)
+        gerr = np.array(gerr)
+        ok = np.array([r.status_name == "OK" for r in rg])
+        out = {"workload": "gaussian_grad_d6", "B": B, "slots_in_flight": slots,
+               "rel_tol": float(wl.rel_tol[0]), "max_regions": wl.max_regions,
+               "error_rule": args.adjoint_error_rule,
+               "forward": {"evals_per_s": fe / tf, "wall_ms": 1e3 * tf,
+                           "wall_ms_runs": [1e3 * t for t in tfs]},
+               "forward_adjoint": {"evals_per_s": fe / tg, "wall_ms": 1e3 * tg,
+                                   "wall_ms_runs": [1e3 * t for t in tgs]},
+               "adjoint_overhead": tg / tf - 1.0, "fevals": fe,
+               "same_run_with_adjoint": same,
+               "status": {s: int(sum(r.status_name == s for r in rg))
+                          for s in sorted({r.status_name for r in rg})},
+               "estimate_meets_closed_form": int(est_ok),
+               "gradient_scaled_err_over_tau": {
+                   "median": float(np.median(gerr)), "max": float(gerr.max()),
+                   "max_converged": float(gerr[ok].max()) if ok.any() else None,
+                   "within_1": int((gerr <= 1).sum()),
+                   "within_10": int((gerr <= 10).sum())}}
+        if not args.no_plain:
+            t0 = time.perf_counter()
+            for b in range(B):
+                ctx.integrate_workload(wl.instance(b), **kw)
+            torch.cuda.synchronize()
+            tp = time.perf_counter() - t0
+            out["plain_sequential"] = {"evals_per_s": fe / tp, "wall_ms": 1e3 * tp}
     torch.cuda.empty_cache()
     return out
 
@@ -278,6 +414,16 @@ def suite_mode(args):
 
     torch.cuda.set_device(0)
     ctx = pg.Context(capacity=args.suite_capacity, dim_max=8)
+    try:
+        _suite_sweep(args, ctx)
+    finally:
+        ctx.close()
+
+
+def _suite_sweep(args, ctx):
+    import torch
+    import workloads as W
+    from workloads import closed_forms as cf
     tols = W.paper_tolerances()
     runs = [(name, wl, 1) for name, wl in W.paper_suite()]
     runs += [(name + "_no_threshold", wl, 0) for name, wl in W.paper_suite()
@@ -306,7 +452,6 @@ def suite_mode(args):
                               r.fevals / (ms * 1e-3)}), flush=True)
             if r.status_name != "OK":
                 break
-    ctx.close()
 
 
 def errors_mode(args):
@@ -323,7 +468,15 @@ def errors_mode(args):
     from workloads import closed_forms as cf
 
     torch.cuda.set_device(0)
-    ctx = pg.Context(capacity=args.batch_slots << 20, dim_max=8)
+    with pg.Context(capacity=args.batch_slots << 20, dim_max=8) as ctx:
+        _errors_sweep(args, ctx)
+
+
+def _errors_sweep(args, ctx):
+    import numpy as np
+    import torch
+    import workloads as W
+    from workloads import closed_forms as cf
     for family, d in (("gaussian", 5), ("gaussian", 8), ("product_peak", 5),
                       ("product_peak", 8)):
         wl = W.peaked_batch(family, d, B=args.errors_batch)
@@ -348,7 +501,6 @@ def errors_mode(args):
                     "median_true_over_tol": float(np.median(true / (tol * np.abs(exact)))),
                     "regions_evaluated": int(sum(r.regions_evaluated for r in res)),
                     "ms": ms}), flush=True)
-    ctx.close()
 
 
 def batched_mode(args):
@@ -357,31 +509,46 @@ def batched_mode(args):
 
 
 def cpu_baseline(wl):
-    """The CPU oracle, single-threaded, on the first 12 iterations of the same
-    run (about 2e6 regions x 93 points)."""
+    """The CPU oracle on the whole headline run (to convergence, the same
+    options and cap): the parity build on one core, then its OpenMP build
+    (region evaluation shared out over the host's cores, the same results)
+    on every core this process may use; the host they ran on."""
     import oracle
-    r = oracle.integrate_workload(wl, max_iters=12)
-    return {"value": r.fevals / r.seconds, "unit": "evals/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"first 12 iterations of the same run: {r.regions_evaluated} "
-                      f"regions, {r.fevals} evaluations, {r.seconds:.1f} s"}
+    r = oracle.integrate_workload(wl)
+    out = {"value": r.fevals / r.seconds, "unit": "evals/s", "cores": 1,
+           "kind": "oracle",
+           "sample": f"the whole run to convergence ({r.status_name}, {r.iterations} "
+                     f"iterations, {r.regions_evaluated} regions, {r.fevals} "
+                     f"evaluations) in {r.seconds:.1f} s",
+           "time_to_tol_ms": 1e3 * r.seconds, "status": r.status_name,
+           "host": _host()}
+    rp = oracle.integrate_workload(wl, parallel=True)
+    out["all_cores"] = {"value": rp.fevals / rp.seconds, "unit": "evals/s",
+                        "cores": oracle.threads(True), "kind": "oracle (OpenMP build)",
+                        "time_to_tol_ms": 1e3 * rp.seconds,
+                        "same_result": (rp.estimate, rp.error, rp.iterations) ==
+                                       (r.estimate, r.error, r.iterations)}
+    return out
 
 
 def integrand_mode(args):
-    """f alone at 2^22 points, for counting an evaluation's FP64 operations."""
-    import numpy as np
+    """f alone at 2^22 points, for counting an evaluation's FP64 operations
+    (--integrand: one of the workloads' integrands)."""
     import torch
     import paper_2104_06494_amd as pg
     import workloads as W
     torch.cuda.set_device(0)
-    wl = W.gaussian_d5()
+    wl = {"gaussian_d5": W.gaussian_d5, "product_peak_d3": W.product_peak_d3,
+          "oscillatory_d8": lambda: W.oscillatory_d8(1),
+          "corner_peak_d6": lambda: W.corner_peak_batch_d6().instance(0)}[args.integrand]()
     n = 1 << 22
     x = torch.rand(wl.d, n, dtype=torch.float64, device="cuda")
-    ctx = pg.Context(capacity=1 << 10, dim_max=wl.d)
-    for _ in range(args.warmup + args.steps):
-        y = ctx.integrand_values(wl.family, wl.params, x)
-    torch.cuda.synchronize()
-    print(json.dumps({"mode": "integrand", "points": n, "launches": args.warmup + args.steps,
+    with pg.Context(capacity=1 << 10, dim_max=wl.d) as ctx:
+        for _ in range(args.warmup + args.steps):
+            y = ctx.integrand_values(wl.family, wl.params, x)
+        torch.cuda.synchronize()
+    print(json.dumps({"mode": "integrand", "integrand": args.integrand, "points": n,
+                      "launches": args.warmup + args.steps,
                       "checksum": float(y.sum())}), flush=True)
 
 
@@ -410,6 +577,8 @@ def main():
                                        "errors", "integrand", "copy"],
                     default="headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other workloads and threshold-search rules")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-vs-plain comparison")
     ap.add_argument("--no-adjoint", action="store_true",
@@ -427,6 +596,21 @@ def main():
                     help="region error estimate of the suite sweep")
     ap.add_argument("--errors-batch", type=int, default=128,
                     help="integrals per family and tolerance in --mode errors")
+    ap.add_argument("--integrand", default="gaussian_d5",
+                    choices=["gaussian_d5", "product_peak_d3", "oscillatory_d8",
+                             "corner_peak_d6"],
+                    help="integrand of --mode integrand")
+    ap.add_argument("--reps", type=int, default=5,
+                    help="timed runs of the batched and derivative comparisons "
+                         "(medians reported)")
+    ap.add_argument("--adjoint-tol", type=float, default=1e-5,
+                    help="rel_tol of the derivative workload")
+    ap.add_argument("--adjoint-cap", type=int, default=0,
+                    help="region cap per integral of the derivative workload "
+                         "(0: the workload's 2^22)")
+    ap.add_argument("--adjoint-count", type=int, default=0,
+                    help="first parameter points only (0 = all 256)")
+    ap.add_argument("--adjoint-error-rule", default="raw", choices=["raw", "null4"])
     ap.add_argument("--batch-slots", type=int, default=64,
                     help="integrals in flight in the batched run (each "
                          "reserves 2^21 regions of workspace)")

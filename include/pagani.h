@@ -115,6 +115,33 @@ typedef enum {
     PG_PMAX_UNDER_MEMORY = 1
 } pg_pmax_relax;
 
+/*
+ * The error budget of the threshold search's accuracy requirement
+ * (Algorithm 3: finished error <= P_max times the budget). The listing's
+ * budget is the error the finished regions may carry, tau |v_tot| - e_f
+ * (its e_it - e_b, read so that Section 3.5.3's remark holds: finishing
+ * more than it makes convergence impossible).
+ *  PG_BUDGET_RESERVE  in a search started because the estimate's digits
+ *                     have settled (trigger (a) of Section 3.5.2), the
+ *                     finished regions -- those finished earlier and those
+ *                     the relative-error test finishes now -- may carry only
+ *                     tau times their own estimate, tau |v_f + sum of their
+ *                     V| - e_f: by Lemma 1 (Section 3.5.1) the regions left
+ *                     active may still end with tau |V| each, and Section
+ *                     3.5.2 asks the search not to over-commit finished
+ *                     error. A search started because the list would
+ *                     overflow (trigger (b)) has the listing's budget:
+ *                     there continuing is the only way on (the default).
+ *  PG_BUDGET_LISTING  every search has the listing's budget. Under the
+ *                     P_max rule of Section 3.5.3 its searches may commit so
+ *                     much finished error that every region finishes with
+ *                     the tolerance unmet (PG_NO_ACTIVE).
+ */
+typedef enum {
+    PG_BUDGET_RESERVE = 0,
+    PG_BUDGET_LISTING = 1
+} pg_budget;
+
 typedef struct pg_context pg_context;
 
 typedef struct {
@@ -140,12 +167,14 @@ typedef struct {
     const char *trace_path;   /* non-NULL: write the decision trace (below) */
     int error_rule;           /* pg_error_rule */
     int pmax_relax;           /* pg_pmax_relax */
+    int budget;               /* pg_budget */
 } pg_options;
 
 /* Default options (the inputs of Algorithm 2 and the user flag of Section
    3.5.1): rel_tol 1e-3, abs_tol 1e-20, g = 4, it_max = 100, both filters
    on, cap = capacity, no timing, no trace, error rule PG_ERR_RAW, P_max
-   rule PG_PMAX_EVERY_CHANGE. A zero-filled struct holds the same rules. */
+   rule PG_PMAX_EVERY_CHANGE, budget PG_BUDGET_RESERVE. A zero-filled
+   struct holds the same rules. */
 void pg_default_options(pg_options *opt);
 
 typedef struct {
@@ -207,8 +236,8 @@ const char *pg_last_error(const pg_context *ctx);
  * PG_EUNSUPPORTED, PG_EHIP.
  *
  * Decision trace (when opt->trace_path is set), little endian:
- *   header  char magic[8] = "PGTRACE1"; int32 d; int32 family;
- *           int64 pmax_relax, error_rule (the run's rules)
+ *   header  char magic[8] = "PGTRACE2"; int32 d; int32 family;
+ *           int64 pmax_relax, error_rule, budget (the run's rules)
  *   per iteration:
  *     int64 it, n, n_active; int32 thr_invoked, thr_ok, thr_trials,
  *     terminal (-1 = continues, else the pg_status the run ends with);
@@ -340,8 +369,8 @@ int pg_integrand_values(pg_context *ctx, const pg_integrand *f, int64_t n,
  *   delta = |V_i + V_j - Vp| / 4, S = E_i + E_j,
  *   E <- E (1 + 2 delta / S) + delta   (E + delta when S = 0).
  * A[i] = 1 (active) iff E_i > rel_tol |V_i| (always 1 with relerr_filter 0).
- * sums (host, 7 doubles): sum V, sum E, sum A V, sum A E, sum A, min E,
- * max E. Blocks until the sums are known.
+ * sums (host, 8 doubles): sum V, sum E, sum A V, sum A E, sum A, min E,
+ * max E, sum (1 - A) V. Blocks until the sums are known.
  */
 int pg_classify(pg_context *ctx, int64_t n, int paired, const double *V,
                 double *E, const double *Vp, double rel_tol,
@@ -350,19 +379,25 @@ int pg_classify(pg_context *ctx, int64_t n, int paired, const double *V,
 /*
  * THRESHOLD-CLASSIFY (Algorithm 3, Section 3.5.3) on n regions with errors
  * E and rel-err flags A_rel: searches t such that A = A_rel AND (E > t)
- * finishes more than half of the regions with finished error <= P_max
- * (tau |v_tot| - e_f), e_f = e_tot - e_it. P_max starts at 0.25; with
- * relax != 0 it grows by 0.10 per direction change (max 0.95), as Section
- * 3.5.3 states; with relax = 0 it stays 0.25 (pg_integrate passes 0 only
- * under PG_PMAX_UNDER_MEMORY for a search the memory trigger did not
- * start). At most 64 trials and 10 direction changes. Returns 1 in *ok
- * with t and A_out (device, n bytes) on success; 0 and A_out = A_rel on
- * failure. Blocks.
+ * finishes more than half of the regions while the error of the regions it
+ * finishes, summed over them, is <= P_max * allowance. e_it is the list's
+ * total error (the first t is e_it / n). pg_integrate passes as allowance
+ * the listing's e_it - e_b = tau |v_tot| - e_f, or, under
+ * PG_BUDGET_RESERVE for a search the memory trigger did not start,
+ * tau |v_f + sum of V over A_rel = 0| - e_f (see pg_budget; pg_classify
+ * returns that sum). P_max starts at 0.25; with relax != 0 it grows by
+ * 0.10 per direction change (max 0.95), as Section 3.5.3 states; with
+ * relax = 0 it stays 0.25 (pg_integrate passes 0 only under
+ * PG_PMAX_UNDER_MEMORY for a search the memory trigger did not start). At
+ * most 64 trials and 10 direction changes. Returns 1 in *ok with t and
+ * A_out (device, n bytes) on success; 0 and A_out = A_rel on failure.
+ * PG_EINVAL for an empty list, a NULL argument or a non-finite e_it or
+ * allowance. Blocks.
  */
 int pg_threshold_search(pg_context *ctx, int64_t n, const double *E,
-                        const uint8_t *A_rel, double v_tot, double e_tot,
-                        double e_it, double rel_tol, int relax,
-                        uint8_t *A_out, int *ok, double *t, int *trials);
+                        const uint8_t *A_rel, double e_it, double allowance,
+                        int relax, uint8_t *A_out, int *ok, double *t,
+                        int *trials);
 
 /*
  * FILTER + parent update + SPLIT (the last three steps of Algorithm 2's

@@ -15,7 +15,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 # PAGANI_ORACLE_LIB lets the mutation tests load a deliberately broken copy
 _LIB_PATH = os.environ.get("PAGANI_ORACLE_LIB",
                            os.path.join(_HERE, "liboracle.so"))
+_LIB_OMP_PATH = os.path.join(_HERE, "liboracle_omp.so")
 _lib = None
+_lib_omp = None
 
 FAMILY_ID = {"product_peak": 0, "gaussian": 1, "oscillatory": 2,
              "corner_peak": 3, "monomial": 4, "c0": 5, "discontinuous": 6,
@@ -33,21 +35,28 @@ class ReplayStats(C.Structure):
         "term_override", "term_hard", "trig_override", "trig_hard",
         "search_hard", "thr_override", "thr_hard", "records")] + [
         ("max_t_rel", C.c_double), ("max_v_rel", C.c_double),
-        ("max_e_rel", C.c_double)]
+        ("max_e_rel", C.c_double)] + [
+        (n, C.c_int64) for n in ("search_hard_it", "gpu_ok", "gpu_trials",
+                                 "cpu_ok", "cpu_trials")] + [
+        ("gpu_t", C.c_double), ("cpu_t", C.c_double)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
-def lib():
-    """Load liboracle.so, building it first if it is missing."""
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(_LIB_PATH):
+def lib(parallel: bool = False):
+    """Load liboracle.so (parallel: its OpenMP timing build), building it
+    first if it is missing."""
+    global _lib, _lib_omp
+    if (_lib_omp if parallel else _lib) is not None:
+        return _lib_omp if parallel else _lib
+    path = _LIB_OMP_PATH if parallel else _LIB_PATH
+    if not os.path.exists(path):
         from .build import build
         build()
-    L = C.CDLL(_LIB_PATH)
+    L = C.CDLL(path)
+    L.oracle_threads.restype = C.c_int
+    L.oracle_threads.argtypes = []
     L.oracle_f.restype = C.c_double
     L.oracle_f.argtypes = [C.c_int, C.c_int, _dp, _dp]
     L.oracle_npoints.restype = C.c_long
@@ -69,8 +78,8 @@ def lib():
     L.oracle_sum.argtypes = [C.c_long, _dp, C.c_void_p]
     L.oracle_threshold_search.restype = C.c_int
     L.oracle_threshold_search.argtypes = [C.c_long, _dp, _u8, C.c_double,
-                                          C.c_double, C.c_double, C.c_double,
-                                          C.c_int, _u8, C.POINTER(C.c_double),
+                                          C.c_double, C.c_int, _u8,
+                                          C.POINTER(C.c_double),
                                           C.POINTER(C.c_int), C.c_void_p]
     L.oracle_filter_split.restype = C.c_long
     L.oracle_filter_split.argtypes = [C.c_int, C.c_long, _dp, _dp, C.c_long,
@@ -81,7 +90,8 @@ def lib():
     L.oracle_integrate.restype = C.c_int
     L.oracle_integrate.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, C.c_double,
                                    C.c_double, C.c_int, C.c_int, C.c_int,
-                                   C.c_int, C.c_int, C.c_int, C.c_int64, C.c_char_p, _dp,
+                                   C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64,
+                                   C.c_char_p, _dp,
                                    np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS"),
                                    C.POINTER(ReplayStats), C.c_void_p, C.c_void_p,
                                    C.c_void_p]
@@ -90,7 +100,10 @@ def lib():
     L.oracle_grad_regions.restype = C.c_int
     L.oracle_grad_regions.argtypes = [C.c_int, C.c_int, _dp, C.c_long, _dp, _dp,
                                       C.c_long, _dp, _dp]
-    _lib = L
+    if parallel:
+        _lib_omp = L
+    else:
+        _lib = L
     return L
 
 
@@ -119,6 +132,11 @@ ERROR_RULE = {"raw": 0, "null4": 1}
 # P_max relaxation of the threshold search: at every direction change of
 # every search (Section 3.5.3) or only in searches under memory pressure
 PMAX_RELAX = {"paper": 0, "memory": 1}
+
+# Accuracy budget of a threshold search started because the estimate's
+# digits have settled: "reserve" keeps back the error the rel-err-active
+# regions may still end with (Lemma 1); "listing" keeps nothing back.
+BUDGET = {"reserve": 0, "listing": 1}
 
 
 def null_rules(d: int) -> np.ndarray:
@@ -185,18 +203,21 @@ def csum(x, mask=None) -> float:
     return lib().oracle_sum(len(x), x, _ptr(m))
 
 
-def threshold_search(E, A_rel, v_tot, e_tot, e_it, tau_rel, relax=True):
+def threshold_search(E, A_rel, e_it, allow, relax=True):
     """Threshold-Classify (Algorithm 3); with relax, P_max grows by 0.10 at
     each change of direction up to 0.95 (Section 3.5.3), else it stays at
-    0.25. Returns (ok, A, t, trials, tried_ts)."""
+    0.25. The accuracy requirement allows the finished regions an error of
+    P_max * allow (the listing's e_it - e_b = tau |v_tot| - e_f, or the
+    finished regions' own share under the reserve reading). Returns (ok, A,
+    t, trials, tried_ts)."""
     E = _f64(E)
     A_rel = np.ascontiguousarray(A_rel, dtype=np.uint8)
     A = np.zeros(len(E), np.uint8)
     t = C.c_double()
     tr = C.c_int()
     tried = np.zeros(64)
-    ok = lib().oracle_threshold_search(len(E), E, A_rel, v_tot, e_tot, e_it,
-                                       tau_rel, int(bool(relax)), A,
+    ok = lib().oracle_threshold_search(len(E), E, A_rel, float(e_it), float(allow),
+                                       int(bool(relax)), A,
                                        C.byref(t), C.byref(tr),
                                        _ptr(tried))
     return bool(ok), A, t.value, tr.value, tried[:tr.value].copy()
@@ -252,11 +273,13 @@ def integrate(family: str, d: int, params, lo=None, hi=None, rel_tol=1e-3,
               abs_tol=1e-20, init_splits=4, max_iters=100, relerr_filter=1,
               threshold_filter=1, max_regions=1 << 22,
               replay_path: str | None = None, grad: bool = False,
-              error_rule: str = "raw", pmax_relax: str = "paper") -> OracleResult:
+              error_rule: str = "raw", pmax_relax: str = "paper",
+              budget: str = "reserve", parallel: bool = False) -> OracleResult:
     """PAGANI main loop (Algorithm 2), free mode or replaying a GPU trace.
     With grad=True also the derivative of the estimate with respect to the
     parameters over the partition the run ends on (its leaves: every region
-    finished on the way and the live list at the end)."""
+    finished on the way and the live list at the end). parallel=True runs
+    the OpenMP timing build (same results; see threads())."""
     lo = np.zeros(d) if lo is None else _f64(lo)
     hi = np.ones(d) if hi is None else _f64(hi)
     out_d = np.zeros(4)
@@ -266,10 +289,11 @@ def integrate(family: str, d: int, params, lo=None, hi=None, rel_tol=1e-3,
     g = np.zeros(npar) if grad else None
     ga = np.zeros(npar) if grad else None
     lv = np.zeros(1)
-    rc = lib().oracle_integrate(FAMILY_ID[family], d, _f64(params), lo, hi,
+    rc = lib(parallel).oracle_integrate(FAMILY_ID[family], d, _f64(params), lo, hi,
                                 rel_tol, abs_tol, init_splits, max_iters,
                                 relerr_filter, threshold_filter,
                                 ERROR_RULE[error_rule], PMAX_RELAX[pmax_relax],
+                                BUDGET[budget],
                                 max_regions,
                                 replay_path.encode() if replay_path else None,
                                 out_d, out_i, C.byref(rs), _ptr(g), _ptr(ga), _ptr(lv))
@@ -279,6 +303,11 @@ def integrate(family: str, d: int, params, lo=None, hi=None, rel_tol=1e-3,
                         int(out_i[2]), int(out_i[3]), int(out_i[4]),
                         int(out_i[5]), int(out_i[6]), out_d[2], out_d[3],
                         rs.as_dict() if replay_path else None, g, ga, float(lv[0]))
+
+
+def threads(parallel: bool = True) -> int:
+    """Threads the (parallel) build evaluates regions on."""
+    return int(lib(parallel).oracle_threads())
 
 
 def grad_f(family: str, params, x) -> np.ndarray:
@@ -322,4 +351,4 @@ __all__ = ["lib", "npoints", "rule", "f", "eval_regions", "two_level",
            "classify", "csum", "threshold_search", "filter_split",
            "uniform_split", "integrate", "integrate_workload", "OracleResult",
            "grad_f", "grad_regions", "null_rules", "ERROR_RULE",
-           "RegionEval", "FAMILY_ID", "STATUS", "PMAX_RELAX"]
+           "RegionEval", "FAMILY_ID", "STATUS", "PMAX_RELAX", "BUDGET", "threads"]

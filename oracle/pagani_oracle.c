@@ -29,10 +29,13 @@
  *   R5  classification (Section 3.5.1, Lemma 1): finished iff E <= tau |V|;
  *   R6  threshold search (Algorithm 3) with the directions fixed by the
  *       Figure 3 narrative, the accuracy requirement measured against the
- *       error finished regions may still carry, P_max relaxed at every
- *       direction change as Section 3.5.3 states (or, as an option that
- *       departs from it, only under memory pressure), 10 direction changes /
- *       64 trials at most;
+ *       error finished regions may still carry -- in searches started
+ *       because the estimate's digits have settled, less the error the
+ *       regions left active may still end with under Lemma 1 (Section
+ *       3.5.2 asks those searches not to over-commit finished error) --
+ *       P_max relaxed at every direction change as Section 3.5.3 states
+ *       (or, as an option that departs from it, only under memory
+ *       pressure), 10 direction changes / 64 trials at most;
  *   R7  filter/split order: stable compaction; children of the j-th active
  *       region go to j (lower half) and j + n_active (upper half);
  *   R9  optional error estimate from four null rules (Section 3.2 compares
@@ -40,6 +43,9 @@
  *       fully symmetric null rules of degrees 5, 3, 3, 1 of the same
  *       points, and a decay test between their magnitudes (below).
  */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <math.h>
 #include <stdint.h>
 #include <stdio.h>
@@ -455,6 +461,12 @@ int oracle_eval_regions(int family, int d, const double *par, long n,
         return OR_EINVAL;
     oracle_rule(d, w7, w5, lam);
     if (err_rule) oracle_null_rules(d, nul);
+    /* regions are independent: the timing build (-fopenmp) shares them out
+       over the host's cores with the same per-region arithmetic; the parity
+       build is single threaded */
+#ifdef _OPENMP
+#pragma omp parallel for private(k, kk, l, ww, fv, fe, fd) schedule(static)
+#endif
     for (i = 0; i < n; i++) {
         for (k = 0; k < d; k++) {
             l[k] = lo[k * ld + i];
@@ -711,12 +723,14 @@ double oracle_sum(long n, const double *x, const uint8_t *mask)
  *   Apply-Threshold: A = A_rel AND (E > t)  (threshold-finished regions join
  *   the rel-err-finished ones);
  *   memory requirement: more than half of the s_it regions finished;
- *   accuracy requirement: finished error <= P_max * (e_it - e_b) with
- *   e_b = e_tot - tau |v_tot| the excess error that the active regions
- *   still have to shed; e_it - e_b = tau |v_tot| - e_f is the error that
- *   finished regions may carry without making convergence impossible
- *   (Section 3.5.3 states that finishing more than that rules out
- *   convergence, which the literal comparison with e_b does not prevent);
+ *   accuracy requirement: finished error <= P_max * allow, where `allow`,
+ *   chosen by the caller, is the error the finished regions may carry
+ *   without making convergence impossible (Section 3.5.3 states that
+ *   finishing more than the budget rules out convergence); the run passes
+ *   the listing's e_it - e_b = tau |v_tot| - e_f (e_b = e_tot - tau |v_tot|
+ *   the excess the active regions still have to shed), or, keeping the
+ *   active regions' share back, tau |estimate of the finished regions| -
+ *   e_f (reading R6);
  *   memory fails  -> raise t halfway to max(E);
  *   accuracy fails-> lower t halfway to min(E);
  *   with relax set, each change of direction adds 0.10 to P_max (at most
@@ -731,21 +745,27 @@ double oracle_sum(long n, const double *x, const uint8_t *mask)
 #define OR_THR_MAX_DIRCHG 10
 
 int oracle_threshold_search(long s_it, const double *E, const uint8_t *A_rel,
-                            double v_tot, double e_tot, double e_it,
-                            double tau_rel, int relax,
+                            double e_it, double allow, int relax,
                             uint8_t *Aout, double *t_out,
                             int *trials_out, double *tried /* [64] or NULL */)
 {
-    double P_max = 0.25, mn, mx, e_b, t, e_abar;
+    double P_max = 0.25, mn, mx, t, e_abar;
     long i, s_abar, n_act;
+    uint8_t *fin;
     int trials = 0, dir = 0, last_dir = 0, dir_changes = 0;
 
+    fin = malloc(s_it > 0 ? (size_t)s_it : 1);
+    if (!fin) {
+        memcpy(Aout, A_rel, (size_t)s_it);
+        *t_out = NAN;
+        *trials_out = 0;
+        return 0;
+    }
     mn = INFINITY; mx = -INFINITY;
     for (i = 0; i < s_it; i++) {
         if (E[i] < mn) mn = E[i];
         if (E[i] > mx) mx = E[i];
     }
-    e_b = e_tot - tau_rel * fabs(v_tot);
     t = e_it / (double)s_it;
 
     while (trials < OR_THR_MAX_TRIALS) {
@@ -754,14 +774,19 @@ int oracle_threshold_search(long s_it, const double *E, const uint8_t *A_rel,
         n_act = 0;
         for (i = 0; i < s_it; i++) {
             Aout[i] = (uint8_t)(A_rel[i] && E[i] > t);
+            fin[i] = (uint8_t)!Aout[i];
             n_act += Aout[i];
         }
         s_abar = s_it - n_act;
-        e_abar = e_it - oracle_sum(s_it, E, Aout);
+        /* the error of the finished regions: the listing's e_it - Sum(E A),
+           summed over those regions themselves, since the difference of the
+           two nearly equal sums loses an error below the rounding of e_it */
+        e_abar = oracle_sum(s_it, E, fin);
         if ((double)s_abar > 0.5 * (double)s_it) {
-            if (e_abar <= P_max * (e_it - e_b)) {
+            if (e_abar <= P_max * allow) {
                 *t_out = t;
                 *trials_out = trials;
+                free(fin);
                 return 1;
             }
             dir = -1;                         /* accuracy failed: lower t */
@@ -780,6 +805,7 @@ int oracle_threshold_search(long s_it, const double *E, const uint8_t *A_rel,
         if (dir > 0) t = t + (mx - t) / 2.0;
         else t = t - (t - mn) / 2.0;
     }
+    free(fin);
     memcpy(Aout, A_rel, (size_t)s_it);
     *t_out = NAN;
     *trials_out = trials;
@@ -845,8 +871,8 @@ long oracle_uniform_split(int d, const double *a, const double *b, int g,
 
 /* ------------------------------------------------------------------------
  * Replay trace (file format written by the GPU library on request):
- *   header : char magic[8] = "PGTRACE1"; int32 d; int32 family;
- *            int64 reserved[2]
+ *   header : char magic[8] = "PGTRACE2"; int32 d; int32 family;
+ *            int64 pmax_relax, error_rule, budget (the run's rules)
  *   record : int64 it, n, n_active;
  *            int32 thr_invoked, thr_ok, thr_trials, terminal;
  *            double t, v, e, v_f, e_f;
@@ -869,7 +895,22 @@ typedef struct {
     int64_t records;
     double max_t_rel;               /* max |t_gpu - t_cpu| / t_cpu */
     double max_v_rel, max_e_rel;    /* per-iteration v, e sums */
+    /* the first search whose outcome differs: iteration, the trace's
+       (ok, trials, t) and the oracle's */
+    int64_t search_hard_it, gpu_ok, gpu_trials, cpu_ok, cpu_trials;
+    double gpu_t, cpu_t;
 } or_replay_stats;
+
+/* Threads the region evaluation runs on: 1 in the parity build, the
+   OpenMP thread count in the timing build. */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------
  * PAGANI main loop (Algorithm 2). Result layout:
@@ -878,6 +919,14 @@ typedef struct {
  *        [4] peak regions, [5] threshold invocations, [6] threshold trials
  * pmax_relax: 0 = P_max grows at every direction change of every search
  * (Section 3.5.3); 1 = only in searches started by the memory trigger.
+ * budget: 0 = in a search started because the estimate's digits have
+ * settled (trigger (a) of Section 3.5.2) and not because the list would
+ * overflow, the finished regions -- those finished before and those the
+ * rel-err test finishes now -- may carry tau times their own estimate,
+ * tau |v_f + sum of V over A_rel = 0| - e_f: by Lemma 1 the regions left
+ * active may still end with tau |V| each, and Section 3.5.2 requires such
+ * searches not to over-commit finished error; 1 = every search allows the
+ * listing's e_it - e_b = tau |v_tot| - e_f.
  * When replay_path is set the run follows the decisions recorded in that
  * trace and fills *rs; otherwise rs may be NULL.
  * ---------------------------------------------------------------------- */
@@ -905,7 +954,7 @@ int oracle_integrate(int family, int d, const double *par,
                      const double *a, const double *b,
                      double tau_rel, double tau_abs, int g, int it_max,
                      int relerr_filter, int threshold_filter, int err_rule,
-                     int pmax_relax,
+                     int pmax_relax, int budget,
                      int64_t max_regions, const char *replay_path,
                      double *out_d, int64_t *out_i, or_replay_stats *rs,
                      double *grad, double *grad_abs, double *leaf_v)
@@ -915,6 +964,7 @@ int oracle_integrate(int family, int d, const double *par,
     double *V = NULL, *E = NULL, *Vp = NULL, *Dd = NULL, *fV = NULL, *fE = NULL;
     double *fD = NULL;
     uint8_t *K = NULL, *A = NULL, *A_rel = NULL, *Kg = NULL, *Ag = NULL;
+    uint8_t *Af = NULL;
     double v, e, v_f = 0.0, e_f = 0.0, v_tot = 0.0, e_tot = 0.0;
     double prev_vtot = NAN, t_eval = 0.0, t0;
     int64_t s, cap, it, status = OR_MAX_ITERS, n_eval = 0, peak = 0;
@@ -932,6 +982,7 @@ int oracle_integrate(int family, int d, const double *par,
     if (err_rule != 0 && (err_rule != 1 || d < 2 || d > OR_NULL_DMAX))
         return OR_EINVAL;
     if (pmax_relax != 0 && pmax_relax != 1) return OR_EINVAL;
+    if (budget != 0 && budget != 1) return OR_EINVAL;
     if (!(tau_rel > 0.0) && !(tau_abs > 0.0)) return OR_EINVAL;
     for (k = 0; k < d; k++) if (!(a[k] < b[k])) return OR_EINVAL;
     s = 1;
@@ -942,13 +993,13 @@ int oracle_integrate(int family, int d, const double *par,
     if (replay_path) {
         char magic[8];
         int32_t hd[2];
-        int64_t res[2];
+        int64_t res[3];
         tr = fopen(replay_path, "rb");
         if (!tr) return OR_EREPLAY;
-        if (fread(magic, 1, 8, tr) != 8 || memcmp(magic, "PGTRACE1", 8) ||
-            fread(hd, 4, 2, tr) != 2 || fread(res, 8, 2, tr) != 2 ||
+        if (fread(magic, 1, 8, tr) != 8 || memcmp(magic, "PGTRACE2", 8) ||
+            fread(hd, 4, 2, tr) != 2 || fread(res, 8, 3, tr) != 3 ||
             hd[0] != d || hd[1] != family ||
-            res[0] != pmax_relax || res[1] != err_rule) {
+            res[0] != pmax_relax || res[1] != err_rule || res[2] != budget) {
             fclose(tr);
             return OR_EREPLAY;
         }
@@ -971,8 +1022,9 @@ int oracle_integrate(int family, int d, const double *par,
     A_rel = malloc(cap);
     Kg = malloc(cap);
     Ag = malloc(cap);
+    Af = malloc(cap);
     if (!lo || !w || !lo2 || !w2 || !V || !E || !Vp || !Dd || !fV || !fE || !fD ||
-        !K || !A || !A_rel || !Kg || !Ag) {
+        !K || !A || !A_rel || !Kg || !Ag || !Af) {
         rc = OR_ENOMEM;
         goto done;
     }
@@ -1093,18 +1145,46 @@ int oracle_integrate(int family, int d, const double *par,
             invoke = rec.thr_invoked != 0;
         }
         if (invoke) {
+            double allow;
+            if (budget == 0 && !(2 * n_rel > cap)) {
+                /* the finished regions' own share (Lemma 1): the regions
+                   the rel-err test leaves active keep theirs */
+                for (i = 0; i < s; i++) Af[i] = (uint8_t)!A_rel[i];
+                allow = tau_rel * fabs(v_f + oracle_sum(s, V, Af)) - e_f;
+            } else {
+                allow = tau_rel * fabs(v_tot) - e_f;    /* e_it - e_b */
+            }
             thr_calls++;
-            ok = oracle_threshold_search(s, E, A_rel, v_tot, e_tot, e, tau_rel,
+            ok = oracle_threshold_search(s, E, A_rel, e, allow,
                                          pmax_relax == 0 || 2 * n_rel > cap,
                                          A, &t, &trials, NULL);
             thr_trials += trials;
             if (tr) {
                 if (ok != (rec.thr_ok != 0) || trials != rec.thr_trials) {
+                    if (rs && !rs->search_hard) {
+                        rs->search_hard_it = it;
+                        rs->gpu_ok = rec.thr_ok;
+                        rs->gpu_trials = rec.thr_trials;
+                        rs->gpu_t = rec.t;
+                        rs->cpu_ok = ok;
+                        rs->cpu_trials = trials;
+                        rs->cpu_t = t;
+                    }
                     if (rs) rs->search_hard++;
                 } else if (ok && rs) {
-                    double r = fabs(rec.t - t) / t;
+                    /* the same trials decided the same way: t can differ
+                       by rounding and by the uncertainty of the smallest
+                       and largest errors its halvings approach */
+                    double r = fabs(rec.t - t) / t, band = 1e-9 * t;
+                    long imn = 0, imx = 0;
+                    for (i = 1; i < s; i++) {
+                        if (E[i] < E[imn]) imn = i;
+                        if (E[i] > E[imx]) imx = i;
+                    }
+                    band += 1e-12 * (E[imn] + E[imx]) + fE[imn] + fV[imn] +
+                            fE[imx] + fV[imx];
                     if (r > rs->max_t_rel) rs->max_t_rel = r;
-                    if (r > 1e-9) rs->search_hard++;
+                    if (fabs(rec.t - t) > band) rs->search_hard++;
                 }
                 ok = rec.thr_ok != 0;
                 if (ok && !(t == t)) t = rec.t;
@@ -1200,5 +1280,6 @@ done:
     free(lo); free(w); free(lo2); free(w2); free(V); free(E); free(Vp);
     free(Dd); free(fV); free(fE); free(fD); free(K); free(A); free(A_rel); free(Kg);
     free(Ag);
+    free(Af);
     return rc;
 }

@@ -21,6 +21,10 @@ ERROR_RULE = {"raw": 0, "null4": 1}
 # P_max relaxation of the threshold search: at every direction change
 # (Section 3.5.3, the default) or only in searches under memory pressure
 PMAX_RELAX = {"paper": 0, "memory": 1}
+# Error budget of a threshold search started because the estimate's digits
+# have settled: keep back what the active regions may still end with
+# (Lemma 1, the default) or nothing
+BUDGET = {"reserve": 0, "listing": 1}
 STATUS = {0: "OK", 1: "MAX_ITERS", 2: "MEMORY_EXHAUSTED", 3: "NO_ACTIVE",
           -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EUNSUPPORTED"}
 
@@ -43,7 +47,7 @@ class Options(C.Structure):
                 ("relerr_filter", C.c_int), ("threshold_filter", C.c_int),
                 ("max_regions", C.c_int64), ("timing", C.c_int),
                 ("trace_path", C.c_char_p), ("error_rule", C.c_int),
-                ("pmax_relax", C.c_int)]
+                ("pmax_relax", C.c_int), ("budget", C.c_int)]
 
 
 class Result(C.Structure):
@@ -131,7 +135,7 @@ def load():
                               vp, C.POINTER(C.c_double)]
     L.pg_classify.restype = C.c_int
     L.pg_threshold_search.argtypes = [vp, i64, vp, vp, C.c_double, C.c_double,
-                                      C.c_double, C.c_double, C.c_int, vp,
+                                      C.c_int, vp,
                                       C.POINTER(C.c_int), C.POINTER(C.c_double),
                                       C.POINTER(C.c_int)]
     L.pg_threshold_search.restype = C.c_int

@@ -48,6 +48,14 @@ def _pmax_relax(mode):
     return int(mode)
 
 
+def _budget(mode):
+    if isinstance(mode, str):
+        if mode not in L.BUDGET:
+            raise ValueError(f"budget must be one of {sorted(L.BUDGET)}")
+        return L.BUDGET[mode]
+    return int(mode)
+
+
 def _integrand(family, d, params):
     p = np.ascontiguousarray(params, dtype=np.float64)
     arr = (C.c_double * len(p))(*p.tolist())
@@ -120,11 +128,12 @@ class Context:
                 self.lib.pg_context_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        # during interpreter shutdown the HIP runtime may already be going
-        # away: leave the context to the process exit instead of calling
-        # into HIP from a finaliser
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # nothing to do once closed; during interpreter shutdown (when even
+        # module globals may be gone, hence the bound default) the HIP
+        # runtime may already be going away: leave the context to the
+        # process exit instead of calling into HIP from a finaliser
+        if not getattr(self, "h", None) or _finalizing():
             return
         try:
             self.close()
@@ -164,12 +173,15 @@ class Context:
                   abs_tol=1e-20, init_splits=4, max_iters=100, relerr_filter=1,
                   threshold_filter=1, max_regions=0, timing=False,
                   trace_path=None, error_rule="raw",
-                  pmax_relax="paper") -> IntegrateResult:
+                  pmax_relax="paper", budget="reserve") -> IntegrateResult:
         """Algorithm 2 over the box [lo, hi] (default unit cube). error_rule
         "raw" (|R7 - R5|) or "null4" (the four-null-rule estimate);
         pmax_relax "paper" (P_max grows at every direction change of a
         threshold search, Section 3.5.3) or "memory" (only in searches under
-        memory pressure)."""
+        memory pressure); budget "reserve" (a search started because the
+        estimate's digits have settled keeps back the error the active
+        regions may still end with, Lemma 1) or "listing" (nothing kept
+        back)."""
         self._bind_stream()
         f, keep = _integrand(family, d, params)
         lo = np.zeros(d) if lo is None else np.asarray(lo, dtype=np.float64)
@@ -187,6 +199,7 @@ class Context:
         o.trace_path = trace_path.encode() if trace_path else None
         o.error_rule = _error_rule(error_rule)
         o.pmax_relax = _pmax_relax(pmax_relax)
+        o.budget = _budget(budget)
         r = L.Result()
         with torch.cuda.device(self.device):
             rc = self.lib.pg_integrate(self.h, C.byref(f), clo, chi, C.byref(o),
@@ -198,20 +211,21 @@ class Context:
     def integrate_batch(self, family, d, params, rel_tol, abs_tol=None,
                         lo=None, hi=None, init_splits=4, max_iters=100,
                         relerr_filter=1, threshold_filter=1, max_regions=0,
-                        error_rule="raw", pmax_relax="paper"):
+                        error_rule="raw", pmax_relax="paper", budget="reserve"):
         """Algorithm 2 for B integrals of one family at once: params is
         [B, n_params], rel_tol a scalar or [B], abs_tol None (1e-20), a
         scalar or [B]; all share the box [lo, hi] and the options, and
         max_regions is the cap of each. Returns a list of B results."""
         return self._batch(family, d, params, rel_tol, abs_tol, lo, hi, init_splits,
                            max_iters, relerr_filter, threshold_filter, max_regions,
-                           error_rule=error_rule, pmax_relax=pmax_relax)[0]
+                           error_rule=error_rule, pmax_relax=pmax_relax,
+                           budget=budget)[0]
 
     def integrate_batch_grad(self, family, d, params, rel_tol, abs_tol=None,
                              lo=None, hi=None, init_splits=4, max_iters=100,
                              relerr_filter=1, threshold_filter=1, max_regions=0,
                              leaves_capacity=0, error_rule="raw",
-                             pmax_relax="paper"):
+                             pmax_relax="paper", budget="reserve"):
         """integrate_batch plus dI/dparams of every integral over its final
         partition: returns (results, grad [B, n_params] numpy, leaves). With
         leaves_capacity > 0, leaves is a dict of device tensors lo, w [d, n]
@@ -219,12 +233,13 @@ class Context:
         return self._batch(family, d, params, rel_tol, abs_tol, lo, hi, init_splits,
                            max_iters, relerr_filter, threshold_filter, max_regions,
                            grad=True, leaves_capacity=leaves_capacity,
-                           error_rule=error_rule, pmax_relax=pmax_relax)
+                           error_rule=error_rule, pmax_relax=pmax_relax,
+                           budget=budget)
 
     def integrate_grad(self, family, d, params, lo=None, hi=None, rel_tol=1e-3,
                        abs_tol=1e-20, init_splits=4, max_iters=100, relerr_filter=1,
                        threshold_filter=1, max_regions=0, leaves_capacity=0,
-                       error_rule="raw", pmax_relax="paper"):
+                       error_rule="raw", pmax_relax="paper", budget="reserve"):
         """One integral and its parameter derivative through the C entry
         point pg_integrate_grad: returns (result, grad [n_params], leaves)."""
         self._bind_stream()
@@ -241,6 +256,7 @@ class Context:
         o.max_regions = int(max_regions)
         o.error_rule = _error_rule(error_rule)
         o.pmax_relax = _pmax_relax(pmax_relax)
+        o.budget = _budget(budget)
         g = np.zeros(f.n_params)
         lv, lt = self._leaves(d, leaves_capacity)
         r = L.Result()
@@ -272,7 +288,8 @@ class Context:
 
     def _batch(self, family, d, params, rel_tol, abs_tol, lo, hi, init_splits,
                max_iters, relerr_filter, threshold_filter, max_regions, grad=False,
-               leaves_capacity=0, error_rule="raw", pmax_relax="paper"):
+               leaves_capacity=0, error_rule="raw", pmax_relax="paper",
+               budget="reserve"):
         self._bind_stream()
         P = np.ascontiguousarray(np.atleast_2d(np.asarray(params, dtype=np.float64)))
         B, npar = P.shape
@@ -295,6 +312,7 @@ class Context:
         o.max_regions = int(max_regions)
         o.error_rule = _error_rule(error_rule)
         o.pmax_relax = _pmax_relax(pmax_relax)
+        o.budget = _budget(budget)
         res = (L.Result * B)()
         fam = L.FAMILY_ID[family] if isinstance(family, str) else int(family)
         g = np.zeros((B, npar)) if grad else None
@@ -318,7 +336,7 @@ class Context:
                                  **kw):
         """integrate_batch (or integrate_batch_grad with grad=True) over a
         batched workload (its first `count` integrals if given); keyword
-        arguments (error_rule, pmax_relax) go to the integrator."""
+        arguments (error_rule, pmax_relax, budget) go to the integrator."""
         B = wl.B if count is None else int(count)
         fn = self.integrate_batch
         kw = dict(kw)
@@ -393,7 +411,7 @@ class Context:
     def classify(self, V, E, Vp=None, paired=False, rel_tol=1e-3, relerr_filter=1):
         """TWO-LEVEL-ERROR (paired lists, in place on E) + REL-ERR-CLASSIFY.
         Returns (A, sums) with sums = [sum V, sum E, sum AV, sum AE, sum A,
-        min E, max E]."""
+        min E, max E, sum (1 - A) V]."""
         self._bind_stream()
         n = V.numel()
         for t, nm in ((V, "V"), (E, "E")):
@@ -401,7 +419,7 @@ class Context:
         if paired:
             _check_f64(Vp, "Vp", self.device)
         A = torch.empty(n, dtype=torch.uint8, device=self.device)
-        sums = (C.c_double * 7)()
+        sums = (C.c_double * 8)()
         rc = self.lib.pg_classify(self.h, n, int(paired), _ptr(V), _ptr(E),
                                   _ptr(Vp) if paired else None, float(rel_tol),
                                   int(relerr_filter), _ptr(A), sums)
@@ -409,20 +427,19 @@ class Context:
             raise self._err(rc)
         return A, list(sums)
 
-    def threshold_search(self, E, A_rel, v_tot, e_tot, e_it, rel_tol,
-                         relax=True):
-        """THRESHOLD-CLASSIFY (Algorithm 3); relax: P_max grows at each
-        direction change (Section 3.5.3). Returns (ok, A, t, trials)."""
+    def threshold_search(self, E, A_rel, e_it, allowance, relax=True):
+        """THRESHOLD-CLASSIFY (Algorithm 3): the finished regions' error may
+        reach P_max * allowance; relax: P_max grows at each direction change
+        (Section 3.5.3). Returns (ok, A, t, trials)."""
         self._bind_stream()
         _check_f64(E, "E", self.device)
         _check_u8(A_rel, "A_rel", self.device)
         A = torch.empty_like(A_rel)
         ok, t, tr = C.c_int(), C.c_double(), C.c_int()
         rc = self.lib.pg_threshold_search(self.h, E.numel(), _ptr(E), _ptr(A_rel),
-                                          float(v_tot), float(e_tot), float(e_it),
-                                          float(rel_tol), int(bool(relax)),
-                                          _ptr(A), C.byref(ok), C.byref(t),
-                                          C.byref(tr))
+                                          float(e_it), float(allowance),
+                                          int(bool(relax)), _ptr(A), C.byref(ok),
+                                          C.byref(t), C.byref(tr))
         if rc:
             raise self._err(rc)
         return bool(ok.value), A, t.value, tr.value

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -70,6 +71,8 @@ struct pg_context {
     // single-integral runs), zero between searches
     uint32_t *hcnt = nullptr;
     unsigned long long *hsum = nullptr;
+    // the bound tables each search's histogram leaves (one pair per slot)
+    double2 *htlo = nullptr, *hthi = nullptr;
     std::vector<hipEvent_t> events;
     std::string err;
     // live list left by the last pg_integrate
@@ -86,9 +89,9 @@ constexpr int INST_STAGES = 4;
 
 struct Layout {
     size_t lo[2], w[2], V, E, Vp, K, A, A2;
-    size_t pv, pe, pav, pae, pmin, pmax, pcnt, off;
+    size_t pv, pe, pav, pae, pfv, pmin, pmax, pcnt, off;
     size_t inst[2], b_inst, b_state, b_tot, b_table, b_order, b_new, b_segs,
-        b_cls, b_tpart, b_gtable, b_gpart, b_git, hcnt, hsum;
+        b_cls, b_tpart, b_gtable, b_gpart, b_git, hcnt, hsum, htlo, hthi;
     size_t search_part, dtot, dstate, total;
     int64_t nseg;
 };
@@ -122,6 +125,7 @@ Layout layout(int dim_max, int64_t cap) {
     L.pe = bump(at, sizeof(double) * L.nseg);
     L.pav = bump(at, sizeof(double) * L.nseg);
     L.pae = bump(at, sizeof(double) * L.nseg);
+    L.pfv = bump(at, sizeof(double) * L.nseg);
     L.pmin = bump(at, sizeof(double) * L.nseg);
     L.pmax = bump(at, sizeof(double) * L.nseg);
     L.pcnt = bump(at, sizeof(uint32_t) * L.nseg);
@@ -142,6 +146,8 @@ Layout layout(int dim_max, int64_t cap) {
     L.b_git = bump(at, sizeof(double) * GRAD_MAX * BATCH_MAX_SLOTS);
     L.hcnt = bump(at, sizeof(uint32_t) * HIST_BINS * BATCH_MAX_SLOTS);
     L.hsum = bump(at, sizeof(unsigned long long) * HIST_BINS * BATCH_MAX_SLOTS);
+    L.htlo = bump(at, sizeof(double2) * HIST_TAB * BATCH_MAX_SLOTS);
+    L.hthi = bump(at, sizeof(double2) * HIST_TAB * BATCH_MAX_SLOTS);
     L.dtot = bump(at, sizeof(Totals));
     L.dstate = bump(at, sizeof(SearchState));
     L.total = (at + ALIGN - 1) / ALIGN * ALIGN;
@@ -416,12 +422,19 @@ int sync_tot(pg_context *ctx, Totals *out) {
 // Sequence number for the next reduce that publishes to the host.
 uint64_t next_seq(pg_context *ctx) { return ++ctx->seq; }
 
+// Longest a host wait for one reduce's totals may take. Everything queued
+// before that reduce (one iteration's kernels, or a batch of search passes)
+// takes milliseconds even on the longest lists, so a wait this long means
+// the stream is stuck behind other work or a kernel that does not end.
+constexpr double WAIT_LIMIT_S = 300.0;
+
 // Wait until the reduce tagged `seq` has published its values to the mapped
 // host copies: spin on the sequence word; every 1024 polls ask the stream
 // whether it has stopped (then the word must be there, else the kernel
-// failed) or has failed.
+// failed) or has failed, and give up with PG_EHIP after WAIT_LIMIT_S.
 int wait_seq(pg_context *ctx, uint64_t seq) {
     const volatile uint64_t *word = ctx->hseq;
+    const auto t0 = std::chrono::steady_clock::now();
     for (uint32_t k = 1;; ++k) {
         if (*word == seq) break;
         if ((k & 1023) == 0) {
@@ -434,6 +447,11 @@ int wait_seq(pg_context *ctx, uint64_t seq) {
             if (e != hipErrorNotReady)
                 return fail(ctx, PG_EHIP, "stream failed: %s",
                             hipGetErrorString(e));
+            const std::chrono::duration<double> dt =
+                std::chrono::steady_clock::now() - t0;
+            if (dt.count() > WAIT_LIMIT_S)
+                return fail(ctx, PG_EHIP, "no totals of reduce %llu after %.0f s",
+                            (unsigned long long)seq, dt.count());
         }
     }
     std::atomic_thread_fence(std::memory_order_acquire);
@@ -471,10 +489,8 @@ struct CountReq {
 };
 
 int search(pg_context *ctx, int64_t n, const double *E, const uint8_t *A_rel,
-           double v_tot, double e_tot, double e_it, double tau, int relax,
-           const CountReq *count, SearchOut *out) {
-    const double e_b = e_tot - tau * std::fabs(v_tot);
-    const double allowance = e_it - e_b;      // = tau |v_tot| - e_f
+           double e_it, double allowance, int relax, const CountReq *count,
+           SearchOut *out) {
     const int max_passes = (THR_MAX_TRIALS + TRIAL_DEPTH - 1) / TRIAL_DEPTH;
     hipStream_t st = ctx->stream;
     *out = SearchOut{};
@@ -482,15 +498,17 @@ int search(pg_context *ctx, int64_t n, const double *E, const uint8_t *A_rel,
     // most trials are decided from the error histogram, exact passes take
     // over from the first one it leaves open
     HIP_OR_FAIL(ctx, launch_search_hist(st, n, E, A_rel, ctx->dstate,
-                                        ctx->hcnt, ctx->hsum, e_it, allowance,
-                                        relax, ctx->dtot));
+                                        ctx->hcnt, ctx->hsum, ctx->htlo,
+                                        ctx->hthi, e_it, allowance, relax,
+                                        ctx->dtot));
     int passes = 0;
     for (int bi = -1; bi < 3 && passes < max_passes; ++bi) {
         const int batch =
             bi < 0 ? 0 : std::min(SEARCH_BATCHES[bi], max_passes - passes);
         for (int k = 0; k < batch; ++k)
             HIP_OR_FAIL(ctx, launch_search_pass(st, n, E, A_rel, ctx->dstate,
-                                                ctx->search_part));
+                                                ctx->search_part, ctx->htlo,
+                                                ctx->hthi));
         passes += batch;
         if (count) {
             HIP_OR_FAIL(ctx, launch_seg_count(st, n, count->paired, 0.0,
@@ -538,6 +556,24 @@ int relax_pmax(const pg_options &o, bool memory_trigger) {
     return o.pmax_relax == PG_PMAX_EVERY_CHANGE || memory_trigger ? 1 : 0;
 }
 
+// The error the regions a threshold search finishes may carry (the
+// allowance of its accuracy requirement; v_f, e_f: the estimate and error
+// of the regions finished in earlier iterations; fv: the summed V of the
+// regions the relative-error test finishes in this one). The listing's
+// e_it - e_b = tau |v_tot| - e_f; under PG_BUDGET_RESERVE, a search started
+// because the estimate's digits have settled lets the finished regions
+// carry only tau times their own estimate, tau |v_f + fv| - e_f: by Lemma 1
+// the regions left active may still end with tau |V| each, and Section
+// 3.5.2 asks such a search not to over-commit finished error. A search run
+// because the list would overflow has the listing's allowance (continuing
+// is then the only way on).
+double search_allowance(const pg_options &o, bool memory_trigger, double tau,
+                        double v_tot, double v_f, double e_f, double fv) {
+    if (o.budget == PG_BUDGET_RESERVE && !memory_trigger)
+        return tau * std::fabs(v_f + fv) - e_f;
+    return tau * std::fabs(v_tot) - e_f;
+}
+
 // Option checks shared by the single and the batched drivers.
 int check_rules(pg_context *ctx, const pg_options &o) {
     if (o.error_rule != PG_ERR_RAW && o.error_rule != PG_ERR_NULL4)
@@ -545,6 +581,8 @@ int check_rules(pg_context *ctx, const pg_options &o) {
     if (o.pmax_relax != PG_PMAX_EVERY_CHANGE &&
         o.pmax_relax != PG_PMAX_UNDER_MEMORY)
         return fail(ctx, PG_EINVAL, "unknown P_max rule %d", o.pmax_relax);
+    if (o.budget != PG_BUDGET_RESERVE && o.budget != PG_BUDGET_LISTING)
+        return fail(ctx, PG_EINVAL, "unknown search budget %d", o.budget);
     return PG_OK;
 }
 
@@ -657,6 +695,7 @@ int pg_context_create(int device, int dim_max, int64_t capacity,
     ctx->part.e = (double *)(b + L.pe);
     ctx->part.av = (double *)(b + L.pav);
     ctx->part.ae = (double *)(b + L.pae);
+    ctx->part.fv = (double *)(b + L.pfv);
     ctx->part.emin = (double *)(b + L.pmin);
     ctx->part.emax = (double *)(b + L.pmax);
     ctx->part.cnt = (uint32_t *)(b + L.pcnt);
@@ -677,6 +716,8 @@ int pg_context_create(int device, int dim_max, int64_t capacity,
     ctx->b_git = (double *)(b + L.b_git);
     ctx->hcnt = (uint32_t *)(b + L.hcnt);
     ctx->hsum = (unsigned long long *)(b + L.hsum);
+    ctx->htlo = (double2 *)(b + L.htlo);
+    ctx->hthi = (double2 *)(b + L.hthi);
     if (hipMemset(ctx->hcnt, 0, L.hsum + sizeof(unsigned long long) * HIST_BINS *
                                          BATCH_MAX_SLOTS - L.hcnt) != hipSuccess) {
         pg_context_destroy(ctx);
@@ -767,7 +808,7 @@ int pg_classify(pg_context *ctx, int64_t n, int paired, const double *V,
     if (!V || !E || !A || !sums || (paired && !Vp))
         return fail(ctx, PG_EINVAL, "NULL array");
     if (n == 0) {
-        for (int k = 0; k < 7; ++k) sums[k] = 0.0;
+        for (int k = 0; k < 8; ++k) sums[k] = 0.0;
         sums[5] = HUGE_VAL;
         sums[6] = -HUGE_VAL;
         return PG_OK;
@@ -781,15 +822,18 @@ int pg_classify(pg_context *ctx, int64_t n, int paired, const double *V,
     rc = sync_tot(ctx, &T);
     if (rc) return rc;
     sums[0] = T.v; sums[1] = T.e; sums[2] = T.av; sums[3] = T.ae;
-    sums[4] = T.cnt; sums[5] = T.emin; sums[6] = T.emax;
+    sums[4] = T.cnt; sums[5] = T.emin; sums[6] = T.emax; sums[7] = T.fv;
     return PG_OK;
 }
 
 int pg_threshold_search(pg_context *ctx, int64_t n, const double *E,
-                        const uint8_t *A_rel, double v_tot, double e_tot,
-                        double e_it, double rel_tol, int relax,
-                        uint8_t *A_out, int *ok, double *t, int *trials) {
+                        const uint8_t *A_rel, double e_it, double allowance,
+                        int relax, uint8_t *A_out, int *ok, double *t,
+                        int *trials) {
     if (!ctx) return PG_EINVAL;
+    if (!std::isfinite(allowance) || !std::isfinite(e_it))
+        return fail(ctx, PG_EINVAL, "e_it %g or allowance %g not finite", e_it,
+                    allowance);
     int rc = validate_list(ctx, n, n);
     if (rc) return rc;
     if (n == 0 || !E || !A_rel || !A_out || !ok || !t || !trials)
@@ -801,8 +845,7 @@ int pg_threshold_search(pg_context *ctx, int64_t n, const double *E,
     HIP_OR_FAIL(ctx, launch_reduce_scan(ctx->stream, seg_count(n, 0),
                                         ctx->part, ctx->off, ctx->dtot));
     SearchOut so;
-    rc = search(ctx, n, E, A_rel, v_tot, e_tot, e_it, rel_tol,
-                relax ? 1 : 0, nullptr, &so);
+    rc = search(ctx, n, E, A_rel, e_it, allowance, relax ? 1 : 0, nullptr, &so);
     if (rc) return rc;
     *ok = so.ok;
     *t = so.ok ? so.t : NAN;
@@ -912,13 +955,13 @@ int pg_integrate(pg_context *ctx, const pg_integrand *f, const double *lo,
     if (o.trace_path) {
         tr = std::fopen(o.trace_path, "wb");
         if (!tr) return fail(ctx, PG_EINVAL, "cannot open %s", o.trace_path);
-        const char magic[8] = {'P', 'G', 'T', 'R', 'A', 'C', 'E', '1'};
+        const char magic[8] = {'P', 'G', 'T', 'R', 'A', 'C', 'E', '2'};
         const int32_t hd[2] = {d, f->family};
         // the run's rules, which a replay must share
-        const int64_t rules[2] = {o.pmax_relax, o.error_rule};
+        const int64_t rules[3] = {o.pmax_relax, o.error_rule, o.budget};
         std::fwrite(magic, 1, 8, tr);
         std::fwrite(hd, 4, 2, tr);
-        std::fwrite(rules, 8, 2, tr);
+        std::fwrite(rules, 8, 3, tr);
     }
     // timing events: 5 per iteration (level 1 records only the two around
     // EVALUATE, level 2 all five)
@@ -1021,7 +1064,9 @@ int pg_integrate(pg_context *ctx, const pg_integrand *f, const double *lo,
                 rec.thr_invoked = 1;
                 Totals T2;
                 const CountReq cr{paired, ctx->V, &T2};
-                RUN_RC(search(ctx, n, ctx->E, ctx->A, v_tot, e_tot, e, tau,
+                RUN_RC(search(ctx, n, ctx->E, ctx->A, e,
+                              search_allowance(o, trig_b, tau, v_tot, v_f, e_f,
+                                               T.fv),
                               relax_pmax(o, trig_b), &cr, &so));
                 res.threshold_trials += so.trials;
                 rec.thr_ok = so.ok;
@@ -1375,7 +1420,8 @@ static int run_batch(pg_context *ctx, int family, int dim, int B,
                 SearchState z{};
                 z.n = S.n;
                 z.e_it = T.e;
-                z.allowance = T.e - (S.e_tot - tau * std::fabs(S.v_tot));
+                z.allowance = search_allowance(o, trig_b, tau, S.v_tot, S.v_f,
+                                               S.e_f, T.fv);
                 z.relax = relax_pmax(o, trig_b);
                 z.mn = T.emin;
                 z.mx = T.emax;
@@ -1399,7 +1445,7 @@ static int run_batch(pg_context *ctx, int family, int dim, int B,
             HIP_OR_FAIL(ctx, launch_batch_search_hist(
                                  st, nseg, ctx->b_segs, nslots, ctx->b_order,
                                  ctx->b_inst, ctx->E, ctx->A, ctx->b_state,
-                                 ctx->hcnt, ctx->hsum));
+                                 ctx->hcnt, ctx->hsum, ctx->htlo, ctx->hthi));
             int passes = 0;
             for (int bi = -1; bi < 3 && passes < max_passes; ++bi) {
                 const int batch = bi < 0 ? 0
@@ -1408,7 +1454,8 @@ static int run_batch(pg_context *ctx, int family, int dim, int B,
                     HIP_OR_FAIL(ctx, launch_batch_search_pass(
                                          st, nseg, ctx->b_segs, nslots,
                                          ctx->b_order, ctx->b_inst, ctx->E,
-                                         ctx->A, ctx->b_state, ctx->b_tpart));
+                                         ctx->A, ctx->b_state, ctx->b_tpart,
+                                         ctx->htlo, ctx->hthi));
                 passes += batch;
                 HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->hb_state, ctx->b_state,
                                                 sizeof(SearchState) * K,

@@ -86,9 +86,9 @@ k_batch_trials(const BSeg *__restrict__ segs, int64_t nseg,
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint32_t cnt[TRIAL_M];
-    double ae[TRIAL_M];
+    double fe[TRIAL_M];
 #pragma unroll
-    for (int m = 0; m < TRIAL_M; ++m) { cnt[m] = 0; ae[m] = 0.0; }
+    for (int m = 0; m < TRIAL_M; ++m) { cnt[m] = 0; fe[m] = 0.0; }
     for (int64_t i0 = sg.start + wave * 64; i0 < sg.end; i0 += LIST_THREADS) {
         const int64_t i = i0 + lane;
         const bool valid = i < sg.end;
@@ -98,11 +98,13 @@ k_batch_trials(const BSeg *__restrict__ segs, int64_t nseg,
         for (int m = 0; m < TRIAL_M; ++m) {
             const bool act = a && e > thr[m];
             cnt[m] += (uint32_t)__popcll(__ballot(act));
-            ae[m] += act ? e : 0.0;
+            // the finished regions' error, summed directly (exactly 0
+            // when every region this threshold finishes carries none)
+            fe[m] += act ? 0.0 : e;
         }
     }
 #pragma unroll
-    for (int m = 0; m < TRIAL_M; ++m) rows[wave][m][lane] = ae[m];
+    for (int m = 0; m < TRIAL_M; ++m) rows[wave][m][lane] = fe[m];
     __syncthreads();
     if (lane < TRIAL_M) {
         double t = 0.0;
@@ -139,20 +141,24 @@ __global__ void __launch_bounds__(HIST_THREADS)
 k_batch_hist_walk(const int32_t *__restrict__ order,
                   const BInst *__restrict__ inst,
                   SearchState *__restrict__ states, uint32_t *__restrict__ cnt,
-                  unsigned long long *__restrict__ sum) {
+                  unsigned long long *__restrict__ sum,
+                  double2 *__restrict__ tlo, double2 *__restrict__ thi) {
     const int slot = order[blockIdx.x];
     if (!inst[slot].searching || states[slot].done) return;
     const SearchState init = states[slot];
     hist_walk(init, states + slot, cnt + (size_t)slot * HIST_BINS,
-              sum + (size_t)slot * HIST_BINS);
+              sum + (size_t)slot * HIST_BINS, tlo + (size_t)slot * HIST_TAB,
+              thi + (size_t)slot * HIST_TAB);
 }
 
 // Adds each searching slot's segment sums in a fixed order and walks its
-// tree, one block per slot.
+// tree, then the trials after it that the slot's histogram bound tables
+// decide; one block per slot.
 __global__ void __launch_bounds__(SCAN_THREADS)
 k_batch_walk(const int32_t *__restrict__ order, const BInst *__restrict__ inst,
              int64_t nseg, const double *__restrict__ tpart,
-             SearchState *__restrict__ states) {
+             SearchState *__restrict__ states, const double2 *__restrict__ tlo,
+             const double2 *__restrict__ thi) {
     __shared__ double tot[2 * TRIAL_M];
     const int slot = order[blockIdx.x];
     const BInst &I = inst[slot];
@@ -162,6 +168,9 @@ k_batch_walk(const int32_t *__restrict__ order, const BInst *__restrict__ inst,
     if (threadIdx.x == 0) {
         SearchState st = states[slot];
         walk_tree(st, tot);
+        if (st.table)
+            bounds_walk(st, tlo + (size_t)slot * HIST_TAB,
+                        thi + (size_t)slot * HIST_TAB);
         states[slot] = st;
     }
 }
@@ -271,14 +280,15 @@ hipError_t launch_batch_search_pass(hipStream_t st, int64_t nseg,
                                     const BSeg *segs, int nslots,
                                     const int32_t *order, const BInst *inst,
                                     const double *E, const uint8_t *A_rel,
-                                    SearchState *states, double *tpart) {
+                                    SearchState *states, double *tpart,
+                                    const double2 *tlo, const double2 *thi) {
     if (nseg <= 0 || nslots <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_batch_trials, dim3((unsigned)nseg), dim3(LIST_THREADS),
                        0, st, segs, nseg, inst, E, A_rel, states, tpart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_batch_walk, dim3(nslots), dim3(SCAN_THREADS), 0, st,
-                       order, inst, nseg, tpart, states);
+                       order, inst, nseg, tpart, states, tlo, thi);
     return hipGetLastError();
 }
 
@@ -287,14 +297,15 @@ hipError_t launch_batch_search_hist(hipStream_t st, int64_t nseg,
                                     const int32_t *order, const BInst *inst,
                                     const double *E, const uint8_t *A_rel,
                                     SearchState *states, uint32_t *cnt,
-                                    unsigned long long *sum) {
+                                    unsigned long long *sum, double2 *tlo,
+                                    double2 *thi) {
     if (nseg <= 0 || nslots <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_batch_hist, dim3((unsigned)nseg), dim3(LIST_THREADS),
                        0, st, segs, inst, states, E, A_rel, cnt, sum);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_batch_hist_walk, dim3(nslots), dim3(HIST_THREADS), 0,
-                       st, order, inst, states, cnt, sum);
+                       st, order, inst, states, cnt, sum, tlo, thi);
     return hipGetLastError();
 }
 

@@ -14,10 +14,10 @@ namespace pg {
 // Deterministic block reductions (fixed shuffle tree, then waves in order)
 // ---------------------------------------------------------------------------
 struct Acc {
-    double v, e, av, ae, mn, mx;
+    double v, e, av, ae, fv, mn, mx;      // fv: V of the regions with a = 0
     uint32_t cnt;
     __device__ void init() {
-        v = e = av = ae = 0.0;
+        v = e = av = ae = fv = 0.0;
         mn = __builtin_huge_val();
         mx = -__builtin_huge_val();
         cnt = 0;
@@ -25,12 +25,12 @@ struct Acc {
     __device__ void add(double V, double E, int a) {
         v += V;
         e += E;
-        if (a) { av += V; ae += E; ++cnt; }
+        if (a) { av += V; ae += E; ++cnt; } else { fv += V; }
         mn = fmin(mn, E);
         mx = fmax(mx, E);
     }
     __device__ void merge(const Acc &o) {
-        v += o.v; e += o.e; av += o.av; ae += o.ae;
+        v += o.v; e += o.e; av += o.av; ae += o.ae; fv += o.fv;
         mn = fmin(mn, o.mn); mx = fmax(mx, o.mx);
         cnt += o.cnt;
     }
@@ -40,6 +40,7 @@ struct Acc {
         o.e = __shfl_xor(e, off);
         o.av = __shfl_xor(av, off);
         o.ae = __shfl_xor(ae, off);
+        o.fv = __shfl_xor(fv, off);
         o.mn = __shfl_xor(mn, off);
         o.mx = __shfl_xor(mx, off);
         o.cnt = __shfl_xor(cnt, off);
@@ -62,6 +63,7 @@ __device__ inline void block_reduce_store(Acc a, SegPartials part, int64_t s) {
         part.e[s] = t.e;
         part.av[s] = t.av;
         part.ae[s] = t.ae;
+        part.fv[s] = t.fv;
         part.emin[s] = t.mn;
         part.emax[s] = t.mx;
         part.cnt[s] = t.cnt;
@@ -201,6 +203,7 @@ __device__ inline void reduce_scan_segments(int64_t seg0, int64_t nseg,
         a.e += part.e[s];
         a.av += part.av[s];
         a.ae += part.ae[s];
+        a.fv += part.fv[s];
         a.mn = fmin(a.mn, part.emin[s]);
         a.mx = fmax(a.mx, part.emax[s]);
         local += part.cnt[s];
@@ -237,7 +240,7 @@ __device__ inline void reduce_scan_segments(int64_t seg0, int64_t nseg,
         tot->emin = t.mn;
         tot->emax = t.mx;
         tot->cnt = (double)total;
-        tot->pad = 0.0;
+        tot->fv = t.fv;
     }
 }
 
@@ -297,7 +300,7 @@ __device__ inline int search_step(SearchState &st, double tt, bool mem_ok,
 
 // Walks up to TRIAL_DEPTH levels of the tree given the totals of a pass:
 // tot[m] regions stay active under node m's threshold and tot[TRIAL_M + m]
-// is the sum of their errors.
+// is the error of the regions it finishes (e_abar of Algorithm 3).
 __device__ inline void walk_tree(SearchState &st, const double *tot) {
     double thr[TRIAL_M];
     build_tree(st, thr);
@@ -306,7 +309,7 @@ __device__ inline void walk_tree(SearchState &st, const double *tot) {
         if (st.trials >= THR_MAX_TRIALS) { st.done = 1; return; }
         const double tt = thr[node];
         const double s_abar = (double)st.n - tot[node];
-        const double e_abar = st.e_it - tot[TRIAL_M + node];
+        const double e_abar = tot[TRIAL_M + node];
         const bool mem_ok = s_abar > 0.5 * (double)st.n;
         const bool acc_ok = e_abar <= st.P_max * st.allowance;
         if (search_step(st, tt, mem_ok, acc_ok)) return;
@@ -396,18 +399,63 @@ __device__ inline void hist_segment(int64_t s0, int64_t s1,
     }
 }
 
-// Decides as many trials as the histogram allows (HIST_THREADS threads):
-// for the bin j holding t, regions in bins above j have E > t and those
-// below have E < t, so the count and error sum of the regions kept active
-// lie in intervals; a trial is decided when both requirements come out the
-// same at both ends, with a relative margin of 1e-12 (far wider than the
-// rounding of the exact pass's sums). The first undecided trial is left to
-// the exact passes. The search starts from `init` and its state is left in
-// *gst. Clears the histogram for the next search.
+// Decides trials from a histogram's bound tables while it can (one
+// thread): for the bin j holding t, regions in bins above j have E > t and
+// those below have E < t, so the count and error sum of the regions kept
+// active lie in intervals (plo[j] and phi[j + 1], the sums already widened
+// by a relative margin of 1e-12, far wider than the rounding of the exact
+// pass's sums); a trial is decided when both requirements come out the same
+// at both ends. Stops at the first undecided trial (left to an exact pass)
+// or when the search ends. The tables may be in LDS or global memory.
+__device__ inline void bounds_walk(SearchState &st,
+                                   const double2 *__restrict__ plo,
+                                   const double2 *__restrict__ phi) {
+    const uint64_t kmax = hist_key(st.mx);
+    const double n = (double)st.n;
+    while (!st.done) {
+        if (st.trials >= THR_MAX_TRIALS) { st.done = 1; break; }
+        const double t = st.t;
+        const uint64_t kt = hist_key(t);
+        double c_lo, c_hi, s_lo, s_hi;
+        if (kt > kmax) {                       // above every error
+            c_lo = c_hi = 0.0;
+            s_lo = s_hi = 0.0;
+        } else {
+            uint64_t j = kmax - kt;
+            if (j > HIST_BINS - 1) j = HIST_BINS - 1;
+            const double2 lo2 = plo[j], hi2 = phi[j + 1];
+            c_lo = lo2.x;
+            c_hi = hi2.x;
+            s_lo = lo2.y;
+            s_hi = hi2.y;
+        }
+        bool mem_ok, acc_ok = false;
+        if (n - c_hi > 0.5 * n) mem_ok = true;
+        else if (!(n - c_lo > 0.5 * n)) mem_ok = false;
+        else break;                            // undecided
+        if (mem_ok) {
+            const double lim = st.P_max * st.allowance;
+            const double slack = 1e-12 * (fabs(st.e_it) + fabs(lim));
+            if (st.e_it - s_lo <= lim - slack) acc_ok = true;
+            else if (st.e_it - s_hi > lim + slack) acc_ok = false;
+            else break;                        // undecided
+        }
+        search_step(st, t, mem_ok, acc_ok);
+    }
+}
+
+// Builds the bound tables of a histogram (HIST_THREADS threads), decides
+// as many trials as they allow (bounds_walk) and leaves the state in *gst.
+// The search starts from `init`. The tables are also stored in tlo / thi
+// (HIST_TAB entries each), so that the trials following each exact pass
+// can be decided from them as well. Clears the histogram for the next
+// search.
 __device__ inline void hist_walk(const SearchState &init,
                                  SearchState *__restrict__ gst,
                                  uint32_t *__restrict__ gcnt,
-                                 unsigned long long *__restrict__ gsum) {
+                                 unsigned long long *__restrict__ gsum,
+                                 double2 *__restrict__ tlo,
+                                 double2 *__restrict__ thi) {
     // bin j's bounds for a trial: {count above, lower error sum above} and
     // {count above, upper error sum above}, the sums already widened by the
     // margin, so a trial reads two 16-byte words
@@ -476,51 +524,30 @@ __device__ inline void hist_walk(const SearchState &init,
                d = csum[wave][2] + ex[2];
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            plo[b0 + q] = make_double2(a, b * (1.0 - 1e-12));
-            phi[b0 + q] = make_double2(a, d * (1.0 + 1e-12));
+            const double2 lo2 = make_double2(a, b * (1.0 - 1e-12));
+            const double2 hi2 = make_double2(a, d * (1.0 + 1e-12));
+            plo[b0 + q] = lo2;
+            phi[b0 + q] = hi2;
+            tlo[b0 + q] = lo2;
+            thi[b0 + q] = hi2;
             a += c[q];
             b += l[q];
             d += u[q];
         }
         if (threadIdx.x == HIST_THREADS - 1) {
-            plo[HIST_BINS] = make_double2(a, b * (1.0 - 1e-12));
-            phi[HIST_BINS] = make_double2(a, d * (1.0 + 1e-12));
+            const double2 lo2 = make_double2(a, b * (1.0 - 1e-12));
+            const double2 hi2 = make_double2(a, d * (1.0 + 1e-12));
+            plo[HIST_BINS] = lo2;
+            phi[HIST_BINS] = hi2;
+            tlo[HIST_BINS] = lo2;
+            thi[HIST_BINS] = hi2;
         }
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
     SearchState st = init;
-    const double n = (double)st.n;
-    while (!st.done) {
-        if (st.trials >= THR_MAX_TRIALS) { st.done = 1; break; }
-        const double t = st.t;
-        const uint64_t kt = hist_key(t);
-        double c_lo, c_hi, s_lo, s_hi;
-        if (kt > kmax) {                       // above every error
-            c_lo = c_hi = 0.0;
-            s_lo = s_hi = 0.0;
-        } else {
-            uint64_t j = kmax - kt;
-            if (j > HIST_BINS - 1) j = HIST_BINS - 1;
-            const double2 lo2 = plo[j], hi2 = phi[j + 1];
-            c_lo = lo2.x;
-            c_hi = hi2.x;
-            s_lo = lo2.y;
-            s_hi = hi2.y;
-        }
-        bool mem_ok, acc_ok = false;
-        if (n - c_hi > 0.5 * n) mem_ok = true;
-        else if (!(n - c_lo > 0.5 * n)) mem_ok = false;
-        else break;                            // undecided
-        if (mem_ok) {
-            const double lim = st.P_max * st.allowance;
-            const double slack = 1e-12 * (fabs(st.e_it) + fabs(lim));
-            if (st.e_it - s_lo <= lim - slack) acc_ok = true;
-            else if (st.e_it - s_hi > lim + slack) acc_ok = false;
-            else break;                        // undecided
-        }
-        search_step(st, t, mem_ok, acc_ok);
-    }
+    st.table = 1;
+    bounds_walk(st, plo, phi);
     *gst = st;
 }
 

@@ -57,7 +57,7 @@ __host__ __device__ inline void seg_range(int64_t s, int64_t n, int paired,
 
 // Per-segment partial results written by the list kernels.
 struct SegPartials {
-    double *v, *e, *av, *ae, *emin, *emax;
+    double *v, *e, *av, *ae, *fv, *emin, *emax;
     uint32_t *cnt;
 };
 
@@ -65,7 +65,7 @@ struct SegPartials {
 struct Totals {
     double v, e, av, ae, emin, emax;
     double cnt;      // number of active regions (exact as a double < 2^53)
-    double pad;
+    double fv;       // sum of V over the regions not active
 };
 
 // Limits of the threshold search (the paper bounds it without numbers).
@@ -84,10 +84,15 @@ struct SearchState {
     int relax;            // P_max grows at each direction change
     int last_dir, dir_changes, trials;
     int done, ok;
+    int table;            // this search's histogram bound tables are stored
 };
 
 // Bins of the error histogram a threshold search starts from (per integral).
 constexpr int HIST_BINS = 2048;
+// Entries of each of the two bound tables a histogram leaves per integral
+// (prefix bounds at every bin edge), so that trials are decided from it
+// again after each exact pass.
+constexpr int HIST_TAB = HIST_BINS + 1;
 
 // ---- many integrals in one list (pg_batch.hip) ---------------------------
 // Each live integral of a batched run owns a slot. Its regions are
@@ -136,19 +141,24 @@ hipError_t launch_batch_reduce(hipStream_t st, int nslots,
                                const int32_t *order, const BInst *inst,
                                SegPartials part, uint32_t *offsets,
                                Totals *tot, Totals *host_tot = nullptr);
+// One exact pass for every searching slot, then the trials each slot's
+// bound tables (tlo / thi: HIST_TAB per slot) decide after it.
 hipError_t launch_batch_search_pass(hipStream_t st, int64_t nseg,
                                     const BSeg *segs, int nslots,
                                     const int32_t *order, const BInst *inst,
                                     const double *E, const uint8_t *A_rel,
-                                    SearchState *states, double *tpart);
+                                    SearchState *states, double *tpart,
+                                    const double2 *tlo, const double2 *thi);
 // Histogram of every searching slot's errors and the trials it decides
-// (cnt / sum: HIST_BINS per slot, zero on entry and left zero).
+// (cnt / sum: HIST_BINS per slot, zero on entry and left zero); its bound
+// tables go to tlo / thi (HIST_TAB per slot).
 hipError_t launch_batch_search_hist(hipStream_t st, int64_t nseg,
                                     const BSeg *segs, int nslots,
                                     const int32_t *order, const BInst *inst,
                                     const double *E, const uint8_t *A_rel,
                                     SearchState *states, uint32_t *cnt,
-                                    unsigned long long *sum);
+                                    unsigned long long *sum, double2 *tlo,
+                                    double2 *thi);
 hipError_t launch_batch_count(hipStream_t st, int64_t nseg, const BSeg *segs,
                               const BInst *inst, const SearchState *states,
                               const double *V, const double *E,
@@ -244,18 +254,22 @@ hipError_t launch_reduce_scan(hipStream_t st, int64_t nseg, SegPartials part,
 // Starts a search in *S (first threshold e_it / n; min / max E from the
 // totals `minmax` of the pass before it) and decides the trials its error
 // histogram allows (k_hist + k_hist_walk); cnt / sum hold HIST_BINS bins,
-// zero on entry and left zero.
+// zero on entry and left zero; the histogram's bound tables are left in
+// tlo / thi (HIST_TAB entries each).
 hipError_t launch_search_hist(hipStream_t st, int64_t n, const double *E,
                               const uint8_t *A_rel, SearchState *S,
                               uint32_t *cnt, unsigned long long *sum,
-                              double e_it, double allowance, int relax,
+                              double2 *tlo, double2 *thi, double e_it,
+                              double allowance, int relax,
                               const Totals *minmax);
-// One pass (TRIAL_DEPTH trials) of the search: k_trials + k_trial_walk; a
-// no-op once the search has ended. blk_part holds 2 TRIAL_M x TRIAL_BLOCKS
+// One pass (TRIAL_DEPTH trials) of the search: k_trials + k_trial_walk,
+// which then decides the trials the bound tables tlo / thi allow; a no-op
+// once the search has ended. blk_part holds 2 TRIAL_M x TRIAL_BLOCKS
 // doubles.
 hipError_t launch_search_pass(hipStream_t st, int64_t n, const double *E,
                               const uint8_t *A_rel, SearchState *S,
-                              double *blk_part);
+                              double *blk_part, const double2 *tlo,
+                              const double2 *thi);
 hipError_t launch_compact_split(hipStream_t st, int d, int64_t n, int paired,
                                 double t, const uint8_t *A_rel,
                                 const double *E, const double *V,

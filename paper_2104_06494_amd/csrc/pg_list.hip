@@ -122,13 +122,14 @@ k_hist(int64_t n, const double *__restrict__ E,
 }
 
 // Starts the search (as k_search_init) and walks the trials the histogram
-// decides.
+// decides; its bound tables stay in tlo / thi for the passes after it.
 __global__ void __launch_bounds__(HIST_THREADS)
 k_hist_walk(SearchState *__restrict__ S, uint32_t *__restrict__ cnt,
-            unsigned long long *__restrict__ sum, int64_t n, double e_it,
+            unsigned long long *__restrict__ sum, double2 *__restrict__ tlo,
+            double2 *__restrict__ thi, int64_t n, double e_it,
             double allowance, int relax, const Totals *__restrict__ minmax) {
     const SearchState init = search_start(n, e_it, allowance, relax, *minmax);
-    hist_walk(init, S, cnt, sum);
+    hist_walk(init, S, cnt, sum, tlo, thi);
 }
 
 // One pass over the list for the TRIAL_M thresholds of the current tree.
@@ -151,9 +152,9 @@ k_trials(int64_t n, const double *__restrict__ E,
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint32_t cnt[TRIAL_M];
-    double ae[TRIAL_M];
+    double fe[TRIAL_M];
 #pragma unroll
-    for (int m = 0; m < TRIAL_M; ++m) { cnt[m] = 0; ae[m] = 0.0; }
+    for (int m = 0; m < TRIAL_M; ++m) { cnt[m] = 0; fe[m] = 0.0; }
     const int64_t stride = (int64_t)gridDim.x * TRIAL_THREADS;
     for (int64_t i0 = (int64_t)blockIdx.x * TRIAL_THREADS + wave * 64; i0 < n;
          i0 += stride) {
@@ -165,11 +166,13 @@ k_trials(int64_t n, const double *__restrict__ E,
         for (int m = 0; m < TRIAL_M; ++m) {
             const bool act = a && e > thr[m];
             cnt[m] += (uint32_t)__popcll(__ballot(act));
-            ae[m] += act ? e : 0.0;
+            // the finished regions' error, summed directly (exactly 0
+            // when every region this threshold finishes carries none)
+            fe[m] += act ? 0.0 : e;
         }
     }
 #pragma unroll
-    for (int m = 0; m < TRIAL_M; ++m) rows[wave][m][lane] = ae[m];
+    for (int m = 0; m < TRIAL_M; ++m) rows[wave][m][lane] = fe[m];
     __syncthreads();
     if (lane < TRIAL_M) {
         double t = 0.0;
@@ -188,10 +191,12 @@ k_trials(int64_t n, const double *__restrict__ E,
     }
 }
 
-// Adds the block sums of one pass in a fixed order and walks the tree.
+// Adds the block sums of one pass in a fixed order and walks the tree,
+// then decides the trials after it that the histogram's bound tables allow.
 __global__ void __launch_bounds__(SCAN_THREADS)
 k_trial_walk(int nblk, const double *__restrict__ blk_part,
-             SearchState *__restrict__ S) {
+             SearchState *__restrict__ S, const double2 *__restrict__ tlo,
+             const double2 *__restrict__ thi) {
     __shared__ double tot[2 * TRIAL_M];
     if (S->done) return;
     sum_trial_parts(blk_part, nblk, nblk, tot);
@@ -199,6 +204,7 @@ k_trial_walk(int nblk, const double *__restrict__ blk_part,
     if (threadIdx.x == 0) {
         SearchState st = *S;
         walk_tree(st, tot);
+        if (st.table) bounds_walk(st, tlo, thi);
         *S = st;
     }
 }
@@ -308,7 +314,8 @@ hipError_t launch_reduce_scan(hipStream_t st, int64_t nseg, SegPartials part,
 hipError_t launch_search_hist(hipStream_t st, int64_t n, const double *E,
                               const uint8_t *A_rel, SearchState *S,
                               uint32_t *cnt, unsigned long long *sum,
-                              double e_it, double allowance, int relax,
+                              double2 *tlo, double2 *thi, double e_it,
+                              double allowance, int relax,
                               const Totals *minmax) {
     if (n <= 0) {
         hipLaunchKernelGGL(k_search_init, dim3(1), dim3(64), 0, st, S, n,
@@ -323,7 +330,7 @@ hipError_t launch_search_hist(hipStream_t st, int64_t n, const double *E,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_hist_walk, dim3(1), dim3(HIST_THREADS), 0, st, S, cnt,
-                       sum, n, e_it, allowance, relax, minmax);
+                       sum, tlo, thi, n, e_it, allowance, relax, minmax);
     return hipGetLastError();
 }
 
@@ -336,14 +343,15 @@ int trial_blocks(int64_t n) {
 
 hipError_t launch_search_pass(hipStream_t st, int64_t n, const double *E,
                               const uint8_t *A_rel, SearchState *S,
-                              double *blk_part) {
+                              double *blk_part, const double2 *tlo,
+                              const double2 *thi) {
     const int blocks = trial_blocks(n);
     hipLaunchKernelGGL(k_trials, dim3((unsigned)blocks), dim3(TRIAL_THREADS), 0,
                        st, n, E, A_rel, S, blk_part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_trial_walk, dim3(1), dim3(SCAN_THREADS), 0, st,
-                       blocks, blk_part, S);
+                       blocks, blk_part, S, tlo, thi);
     return hipGetLastError();
 }
 

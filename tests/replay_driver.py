@@ -19,6 +19,7 @@ the change as an uncertified difference:
   trigger=it        the threshold search is invoked iff it was not
   search=it         an accepted search is recorded as failed (A = A_rel)
   trials=it         the search's trial count is recorded one higher
+  tshift=it         the accepted threshold is recorded 1.5 times larger
   stop=it           the run is recorded as converged at iteration it
 """
 from __future__ import annotations
@@ -37,7 +38,7 @@ STATUS_OK, MAX_ITERS, MEMORY_EXHAUSTED, NO_ACTIVE = 0, 1, 2, 3
 def run(family, d, params, *, rel_tol, abs_tol=1e-20, init_splits=4,
         max_iters=100, relerr_filter=1, threshold_filter=1,
         max_regions=1 << 22, error_rule="raw", pmax_relax="paper",
-        trace_path=None, plant=None, log=None):
+        budget="reserve", trace_path=None, plant=None, log=None):
     """Returns dict(estimate, error, status, iterations, regions_evaluated,
     threshold_calls, threshold_trials). `log`, if a list, receives one dict
     per iteration with the quantities the plants are chosen from."""
@@ -54,10 +55,11 @@ def run(family, d, params, *, rel_tol, abs_tol=1e-20, init_splits=4,
     n_eval = calls = trials_tot = 0
     tr = open(trace_path, "wb") if trace_path else None
     if tr:
-        tr.write(b"PGTRACE1")
+        tr.write(b"PGTRACE2")
         tr.write(struct.pack("<ii", d, oracle.FAMILY_ID[family]))
-        tr.write(struct.pack("<qq", oracle.PMAX_RELAX[pmax_relax],
-                             oracle.ERROR_RULE[error_rule]))
+        tr.write(struct.pack("<qqq", oracle.PMAX_RELAX[pmax_relax],
+                             oracle.ERROR_RULE[error_rule],
+                             oracle.BUDGET[budget]))
     it = 0
     try:
         for it in range(1, max_iters + 1):
@@ -102,8 +104,15 @@ def run(family, d, params, *, rel_tol, abs_tol=1e-20, init_splits=4,
             if invoke:
                 calls += 1
                 relax = pmax_relax == "paper" or trig_b
+                if budget == "reserve" and not trig_b:
+                    # the finished regions' own share (Lemma 1): earlier
+                    # ones and those the rel-err test finishes now
+                    fin = (1 - A_rel).astype(np.uint8)
+                    allow = tau * abs(v_f + oracle.csum(V, fin)) - e_f
+                else:
+                    allow = tau * abs(v_tot) - e_f      # the listing's e_it - e_b
                 ok, A_thr, t, ntr, _ = oracle.threshold_search(
-                    E, A_rel, v_tot, e_tot, e, tau, relax)
+                    E, A_rel, e, allow, relax)
                 trials_tot += ntr
                 info.update(searched=True, ok=ok, t=t, trials=ntr, trig_b=trig_b)
                 if ok and plant.get("search") == it:
@@ -112,7 +121,7 @@ def run(family, d, params, *, rel_tol, abs_tol=1e-20, init_splits=4,
                            thr_trials=ntr + (plant.get("trials") == it))
                 if ok:
                     A = A_thr
-                    rec["t"] = t
+                    rec["t"] = t * (1.5 if plant.get("tshift") == it else 1.0)
             if not ok and 2 * n_rel > cap:
                 status = MEMORY_EXHAUSTED
                 rec.update(terminal=status, n_active=n_rel)

@@ -68,29 +68,37 @@ def _check_against_single(ctx, wl, results, **kw):
         _assert_same_run(rb, rp, b)
 
 
-def _check_closed_forms(wl, results, pmax):
-    """OK integrals meet their tolerance against the closed form; NO_ACTIVE
-    ones (every region finished, the summed error just above tau |v|; the
-    P_max rule of Section 3.5.3 leaves these) still have estimates within
-    it. Returns the number that converged."""
+def _check_closed_forms(wl, results, pmax, misses=()):
+    """OK integrals meet their tolerance against the closed form, except the
+    listed ones, which must still lie within 3 tau of it (the estimated
+    error of a converged run can fall short of the true one); NO_ACTIVE
+    ones (every region finished, the summed error just above tau |v|, which
+    the P_max rule of Section 3.5.3 can leave) are honest near misses.
+    Returns the number that converged."""
     n_ok = 0
     for b, r in enumerate(results):
         if r.status_name not in ("OK", "NO_ACTIVE"):
             continue
         exact = cf.exact(wl.family, wl.params[b], wl.d)
-        check_free_run(r, exact, wl.rel_tol[b], allow_no_active=pmax == "paper")
+        if b in misses:
+            assert r.status_name == "OK", (b, r)
+            assert abs(r.estimate - exact) <= 3 * wl.rel_tol[b] * abs(exact), (b, r)
+        else:
+            check_free_run(r, exact, wl.rel_tol[b], allow_no_active=pmax == "paper")
         n_ok += r.status_name == "OK"
     return n_ok
 
 
-@pytest.mark.parametrize("pmax", ["paper", "memory"])
-def test_batch_equals_single_runs(pmax):
-    """16 integrals, all in flight at once, under both P_max rules."""
-    _say("batch-vs-single B=16", pmax)
+@pytest.mark.parametrize("pmax,budget", [("paper", "reserve"), ("paper", "listing"),
+                                         ("memory", "reserve")])
+def test_batch_equals_single_runs(pmax, budget):
+    """16 integrals, all in flight at once, under both P_max rules and both
+    search budgets."""
+    _say("batch-vs-single B=16", pmax, budget)
     wl = _small_corner_batch(16, seed=40)
     ctx = _ctx(16 * wl.max_regions, wl.d)
-    res = ctx.integrate_batch_workload(wl, pmax_relax=pmax)
-    _check_against_single(ctx, wl, res, pmax_relax=pmax)
+    res = ctx.integrate_batch_workload(wl, pmax_relax=pmax, budget=budget)
+    _check_against_single(ctx, wl, res, pmax_relax=pmax, budget=budget)
     _check_closed_forms(wl, res, pmax)
     ctx.close()
 
@@ -164,17 +172,18 @@ def test_batch_against_oracle_directly():
 
 def test_batch_headline_sample():
     """The first 24 integrals of the 1024-integral d=6 corner-peak batch at
-    its full cap (2^21 regions each, 8 in flight), against single runs.
-    Some integrals at the tightest tolerances end NO_ACTIVE: every region
-    left passes the relative-error test while the error of the regions
-    finished earlier (by that test and by threshold calls) already exceeds
-    the tolerance; the single runs end the same way."""
+    its full cap (2^21 regions each, 8 in flight), against single runs, and
+    the closed forms. With the default rules (every direction change
+    relaxes P_max, a reserve for the active regions) each of the first 128
+    integrals converges in the oracle, so every one must end OK here; the
+    oracle's integral 7 (tau 9e-6) ends 2.5 tau from its closed form with an
+    estimated error of 0.86 tau, and so does the GPU's."""
     _say("batch-headline-sample")
     wl = W.corner_peak_batch_d6()
     ctx = _ctx(8 * wl.max_regions, wl.d)
     res = ctx.integrate_batch_workload(wl, count=24)
     _check_against_single(ctx, wl, res)
-    _check_closed_forms(wl, res, "paper")
+    assert _check_closed_forms(wl, res, "paper", misses=(7,)) == 24
     ctx.close()
 
 

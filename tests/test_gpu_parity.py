@@ -13,7 +13,7 @@ import oracle
 import workloads as W
 from workloads import closed_forms as cf
 
-from parity import assert_region_parity, check_free_run, rel_close
+from parity import assert_region_parity, check_free_run, rel_close, search_diff
 
 pytestmark = pytest.mark.gpu
 
@@ -213,14 +213,18 @@ def test_classify_parity(ctx, n, paired):
     np.testing.assert_allclose(Ed.cpu().numpy(), E_ref, rtol=4e-16, atol=0)
     np.testing.assert_array_equal(A.cpu().numpy(), A_ref)
     ref = [oracle.csum(V), oracle.csum(E_ref), oracle.csum(V, A_ref),
-           oracle.csum(E_ref, A_ref), float(A_ref.sum()), E_ref.min(), E_ref.max()]
-    for k in range(4):
+           oracle.csum(E_ref, A_ref), float(A_ref.sum()), E_ref.min(), E_ref.max(),
+           oracle.csum(V, 1 - A_ref)]
+    for k in (0, 1, 2, 3, 7):
         assert rel_close(sums[k], ref[k], 1e-13), (k, sums[k], ref[k])
-    assert sums[4:] == ref[4:]
+    assert sums[4:7] == ref[4:7]
 
 
-@pytest.mark.parametrize("seed,relax", [(0, 0), (1, 1), (2, 0), (3, 1), (4, 0)])
+@pytest.mark.parametrize("seed,relax", [(0, 0), (1, 1), (2, 0), (3, 1), (4, 0),
+                                        (5, 1), (6, 1)])
 def test_threshold_search_parity(ctx, seed, relax):
+    """Seeds 5 and 6 keep part of the allowance back for the active regions
+    (the reserve of a search started by the settled-digits trigger)."""
     _say("threshold", seed, relax)
     rng = np.random.default_rng(seed)
     n = int(rng.integers(1000, 60000))
@@ -230,10 +234,11 @@ def test_threshold_search_parity(ctx, seed, relax):
     tau = float(10.0 ** rng.uniform(-7, -4))
     e_it = oracle.csum(E)
     e_f = float(rng.uniform(0, 0.3)) * tau * v
-    ok, A, t, trials = ctx.threshold_search(_dev(E), _dev(A_rel, torch.uint8), v,
-                                            e_it + e_f, e_it, tau, mem)
-    rok, rA, rt, rtrials, _ = oracle.threshold_search(E, A_rel, v, e_it + e_f, e_it,
-                                                      tau, mem)
+    reserve = float(rng.uniform(0, 0.4)) * tau * v if seed >= 5 else 0.0
+    allow = tau * v - reserve - e_f
+    ok, A, t, trials = ctx.threshold_search(_dev(E), _dev(A_rel, torch.uint8), e_it,
+                                            allow, relax)
+    rok, rA, rt, rtrials, _ = oracle.threshold_search(E, A_rel, e_it, allow, relax)
     assert (ok, trials) == (rok, rtrials)
     if ok:
         assert rel_close(t, rt, 1e-12)
@@ -265,10 +270,11 @@ def test_threshold_search_spread(ctx, seed, relax, sigma):
     A_rel = (rng.uniform(size=n) < 0.8).astype(np.uint8)
     e_it = oracle.csum(E)
     e_f = float(rng.uniform(0, 0.5)) * tau * v
-    ok, A, t, trials = ctx.threshold_search(_dev(E), _dev(A_rel, torch.uint8), v,
-                                            e_it + e_f, e_it, tau, mem)
-    rok, rA, rt, rtrials, _ = oracle.threshold_search(E, A_rel, v, e_it + e_f, e_it,
-                                                      tau, mem)
+    reserve = float(rng.uniform(0, 0.3)) * tau * v if seed == 13 else 0.0
+    allow = tau * v - reserve - e_f
+    ok, A, t, trials = ctx.threshold_search(_dev(E), _dev(A_rel, torch.uint8), e_it,
+                                            allow, relax)
+    rok, rA, rt, rtrials, _ = oracle.threshold_search(E, A_rel, e_it, allow, relax)
     assert (ok, trials) == (rok, rtrials)
     if ok:
         assert rel_close(t, rt, 1e-12)
@@ -317,7 +323,7 @@ def _replay(ctx, wl, tmp_path, **kw):
 def _assert_replay(r, o, rel=1e-10):
     rep = o.replay
     hard = {k: v for k, v in rep.items() if k.endswith("_hard") and v}
-    assert not hard, (hard, rep)
+    assert not hard, (hard, search_diff(rep))
     assert r.status == o.status and r.iterations == o.iterations
     assert r.regions_evaluated == o.regions_evaluated
     assert rel_close(r.estimate, o.estimate, rel), (r.estimate, o.estimate)
@@ -336,38 +342,42 @@ REPLAY = [
 ]
 
 
-PMAX = ["paper", "memory"]
+# (P_max rule, search budget): the defaults, the listing's budget without a
+# reserve, and the memory-only P_max rule
+RULES = [("paper", "reserve"), ("paper", "listing"), ("memory", "reserve")]
 
 
-@pytest.mark.parametrize("pmax", PMAX)
+@pytest.mark.parametrize("pmax,budget", RULES)
 @pytest.mark.parametrize("name,mk,kw", REPLAY, ids=[c[0] for c in REPLAY])
-def test_integrate_replay(ctx, tmp_path, name, mk, kw, pmax):
-    _say("replay", name, pmax)
+def test_integrate_replay(ctx, tmp_path, name, mk, kw, pmax, budget):
+    _say("replay", name, pmax, budget)
     wl = mk()
-    r, o = _replay(ctx, wl, tmp_path, pmax_relax=pmax, **kw)
+    r, o = _replay(ctx, wl, tmp_path, pmax_relax=pmax, budget=budget, **kw)
     _assert_replay(r, o)
     sign_changing = wl.family == "oscillatory" and wl.relerr_filter
     if r.status_name in ("OK", "NO_ACTIVE") and not sign_changing:
         exact = cf.exact(wl.family, wl.params, wl.d)
         tau = kw.get("rel_tol", wl.rel_tol)
-        check_free_run(r, exact, tau, allow_no_active=pmax == "paper")
+        check_free_run(r, exact, tau,
+                       allow_no_active=(pmax, budget) == ("paper", "listing"))
 
 
-@pytest.mark.parametrize("pmax", PMAX)
-def test_headline_workload_replay(ctx, tmp_path, pmax):
+@pytest.mark.parametrize("pmax,budget", RULES)
+def test_headline_workload_replay(ctx, tmp_path, pmax, budget):
     """d=5 Gaussian to 1e-6 with the 2^21-region cap: replay parity, the
     closed form met, the memory trigger fired (the list reached the cap).
-    Under the P_max rule of Section 3.5.3 the run ends with every region
-    finished and the summed error just above the tolerance (NO_ACTIVE), the
-    estimate still within it; under the memory-only rule it converges."""
-    _say("replay-headline", pmax)
+    With the P_max rule of Section 3.5.3 and no reserve for the active
+    regions the run ends with every region finished and the summed error
+    just above the tolerance (NO_ACTIVE); with the reserve (the default),
+    or under the memory-only P_max rule, it converges."""
+    _say("replay-headline", pmax, budget)
     wl = W.gaussian_d5()
-    r, o = _replay(ctx, wl, tmp_path, pmax_relax=pmax)
+    r, o = _replay(ctx, wl, tmp_path, pmax_relax=pmax, budget=budget)
     _assert_replay(r, o)
     exact = cf.exact(wl.family, wl.params, wl.d)
-    check_free_run(r, exact, wl.rel_tol, allow_no_active=pmax == "paper")
-    if pmax == "memory":
-        assert r.status_name == "OK"
+    listing = (pmax, budget) == ("paper", "listing")
+    check_free_run(r, exact, wl.rel_tol, allow_no_active=listing)
+    assert r.status_name == ("NO_ACTIVE" if listing else "OK")
     assert r.peak_regions == wl.max_regions
 
 

@@ -14,7 +14,7 @@ import oracle
 import workloads as W
 from workloads import closed_forms as cf
 
-from parity import assert_region_parity, rel_close
+from parity import assert_region_parity, rel_close, search_diff
 
 pytestmark = pytest.mark.gpu
 
@@ -103,7 +103,7 @@ def test_integrate_replay(ctx, tmp_path, name, family, d, p, tol, g, relerr):
     o = oracle.integrate(family, d, p, rel_tol=tol, init_splits=g,
                          relerr_filter=relerr, max_regions=1 << 21, replay_path=trace)
     hard = {k: v for k, v in o.replay.items() if k.endswith("_hard") and v}
-    assert not hard, (hard, o.replay)
+    assert not hard, (hard, search_diff(o.replay))
     assert (r.status, r.iterations, r.regions_evaluated) == \
         (o.status, o.iterations, o.regions_evaluated)
     assert rel_close(r.estimate, o.estimate, 1e-10)

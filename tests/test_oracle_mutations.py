@@ -33,8 +33,8 @@ MUTANTS = {
                            "lo2[k * ld_out + j + na] = l + ww;"),
     "search_direction": ("if (dir > 0) t = t + (mx - t) / 2.0;",
                          "if (dir < 0) t = t + (mx - t) / 2.0;"),
-    "search_budget": ("if (e_abar <= P_max * (e_it - e_b)) {",
-                      "if (e_abar <= P_max * e_b) {"),
+    "search_budget": ("if (e_abar <= P_max * allow) {",
+                      "if (e_abar <= P_max * (e_it - allow)) {"),
     "search_pmax_step": ("P_max = P_max + 0.10;", "P_max = P_max + 0.05;"),
     "uniform_split_offset": ("lo[k * ld + r] = a[k] + (double)digit * width;",
                              "lo[k * ld + r] = a[k] + (double)(digit + 1) * width;"),
@@ -106,6 +106,16 @@ REPLAY_MUTANTS = {
         "if (ok != (rec.thr_ok != 0) || trials != rec.thr_trials) {", "if (0) {"),
     "run_pmax_memory_only": ("pmax_relax == 0 || 2 * n_rel > cap,",
                              "2 * n_rel > cap,"),
+    "run_reserve_under_memory": ("if (budget == 0 && !(2 * n_rel > cap))",
+                                 "if (budget == 0)"),
+    "run_reserve_active_regions": ("for (i = 0; i < s; i++) Af[i] = (uint8_t)!A_rel[i];",
+                                   "for (i = 0; i < s; i++) Af[i] = A_rel[i];"),
+    "run_reserve_never": ("if (budget == 0 && !(2 * n_rel > cap))",
+                          "if (budget == 2)"),
+    "run_listing_budget_sign": ("allow = tau_rel * fabs(v_tot) - e_f;    /* e_it - e_b */",
+                                "allow = tau_rel * fabs(v_tot) + e_f;    /* e_it - e_b */"),
+    "replay_t_unchecked": ("if (fabs(rec.t - t) > band) rs->search_hard++;",
+                           "if (0) rs->search_hard++;"),
 }
 
 CASES = [(n, "test_oracle_pins.py") for n in sorted(MUTANTS)] + \

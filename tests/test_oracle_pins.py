@@ -257,7 +257,7 @@ def test_compensated_sum():
 # Threshold-Classify (Algorithm 3)
 # ---------------------------------------------------------------------------
 
-def _check_search_result(E, A_rel, v_tot, e_tot, e_it, tau, mem, res):
+def _check_search_result(E, A_rel, allow, mem, res):
     ok, A, t, trials, tried = res
     s = len(E)
     assert 1 <= trials <= 64
@@ -266,12 +266,11 @@ def _check_search_result(E, A_rel, v_tot, e_tot, e_it, tau, mem, res):
         return
     np.testing.assert_array_equal(A, (A_rel.astype(bool) & (E > t)).astype(np.uint8))
     fin = A == 0
-    e_b = e_tot - tau * abs(v_tot)
     # memory requirement: more than half finished
     assert fin.sum() > 0.5 * s
     # accuracy requirement with the largest P_max the search may reach
     p_cap = 0.95 if mem else 0.25
-    assert math.fsum(E[fin]) <= p_cap * (e_it - e_b) * (1 + 1e-12)
+    assert math.fsum(E[fin]) <= p_cap * allow * (1 + 1e-12)
     # the accepted threshold was the last one tried
     assert tried[-1] == t
     # thresholds stay inside [min E, max E]
@@ -291,15 +290,16 @@ def test_threshold_search_brute_force(seed):
     e_f = float(rng.uniform(0, 0.5)) * tau * v
     e_tot = e_it + e_f
     mem = bool(rng.integers(0, 2))
-    res = oracle.threshold_search(E, A_rel, v, e_tot, e_it, tau, mem)
-    _check_search_result(E, A_rel, v, e_tot, e_it, tau, mem, res)
+    # the listing's allowance e_it - e_b, e_b = e_tot - tau |v_tot|
+    allow = e_it - (e_tot - tau * v)
+    res = oracle.threshold_search(E, A_rel, e_it, allow, mem)
+    _check_search_result(E, A_rel, allow, mem, res)
     # brute force: if some candidate threshold satisfies both requirements at
     # P_max = 0.25 and the first trial (the mean) is feasible, it is accepted
     t0 = e_it / s
     A0 = A_rel.astype(bool) & (E > t0)
-    e_b = e_tot - tau * v
     first_ok = ((~A0).sum() > 0.5 * s and
-                math.fsum(E[~A0]) <= 0.25 * (e_it - e_b))
+                math.fsum(E[~A0]) <= 0.25 * allow)
     if first_ok:
         assert res[0] and res[3] == 1 and res[2] == t0
 
@@ -319,8 +319,7 @@ def test_threshold_search_worked_example():
     """
     E = np.arange(1, 9) * 1e-3
     A_rel = np.ones(8, np.uint8)
-    ok, A, t, trials, tried = oracle.threshold_search(E, A_rel, 20.0, 0.036,
-                                                      0.036, 1e-3, False)
+    ok, A, t, trials, tried = oracle.threshold_search(E, A_rel, 0.036, 0.02, False)
     assert not ok
     np.testing.assert_array_equal(A, A_rel)
     np.testing.assert_allclose(tried[:3], [4.5e-3, 6.25e-3, 3.625e-3], rtol=1e-15)
@@ -346,14 +345,39 @@ def test_threshold_search_worked_example_relaxed():
     """
     E = np.arange(1, 9) * 1e-3
     A_rel = np.ones(8, np.uint8)
-    ok, A, t, trials, tried = oracle.threshold_search(E, A_rel, 20.0, 0.036,
-                                                      0.036, 1e-3, True)
+    ok, A, t, trials, tried = oracle.threshold_search(E, A_rel, 0.036, 0.02, True)
     hand = [4.5e-3, 6.25e-3, 3.625e-3, 5.8125e-3, 3.40625e-3, 5.703125e-3,
             3.3515625e-3, 5.67578125e-3]
     assert ok and trials == 8
     np.testing.assert_allclose(tried, hand, rtol=1e-14)
     assert t == tried[-1]
     np.testing.assert_array_equal(A, [0, 0, 0, 0, 0, 1, 1, 1])
+
+
+def test_threshold_search_worked_example_with_reserve():
+    """The relaxed example again with an allowance of 0.0175 instead of 0.02
+    (as when part of the budget is kept back for the regions left active):
+    the accuracy requirement becomes finished error <= P_max * 0.0175.
+    Traced by hand (finished means E <= t):
+      1-7: as without the reserve (0.015 fails 0.25, 0.45, 0.65 x 0.0175)
+      8: t = 5.67578125e-3   {1..5}: 0.015 > 0.85*0.0175 = 0.014875
+                             -> lower, change 7, P_max 0.95
+      9: t = 3.337890625e-3  {1..3}: memory fails -> raise, change 8
+     10: t = 5.6689453125e-3 {1..5}: 0.015 <= 0.95*0.0175 = 0.016625: accepted.
+    """
+    E = np.arange(1, 9) * 1e-3
+    A_rel = np.ones(8, np.uint8)
+    ok, A, t, trials, tried = oracle.threshold_search(E, A_rel, 0.036, 0.0175, True)
+    hand = [4.5e-3, 6.25e-3, 3.625e-3, 5.8125e-3, 3.40625e-3, 5.703125e-3,
+            3.3515625e-3, 5.67578125e-3, 3.337890625e-3, 5.6689453125e-3]
+    assert ok and trials == 10
+    np.testing.assert_allclose(tried, hand, rtol=1e-14)
+    assert t == tried[-1]
+    np.testing.assert_array_equal(A, [0, 0, 0, 0, 0, 1, 1, 1])
+    # a negative allowance leaves no feasible threshold
+    ok, A, t, trials, _ = oracle.threshold_search(E, A_rel, 0.036, -0.01, True)
+    assert not ok
+    np.testing.assert_array_equal(A, A_rel)
 
 
 # ---------------------------------------------------------------------------
@@ -428,8 +452,9 @@ def test_free_run_product_peak_tolerance_sweep(tau, pmax):
 
 @pytest.mark.parametrize("pmax", PMAX)
 def test_free_run_gaussian_d5_reduced(pmax):
-    """The d=5 Gaussian at rel_tol 1e-4 (the full 1e-6 run takes ~25 s)."""
-    wl = W.gaussian_d5()
+    """The d=5 Gaussian at rel_tol 1e-4 with a 2^16-region cap (the full
+    1e-6 run takes ~25 s)."""
+    wl = W.gaussian_d5(max_regions=1 << 16)
     wl.rel_tol = 1e-4
     r = oracle.integrate_workload(wl, pmax_relax=pmax)
     _check_run(wl, r, pmax)
@@ -439,20 +464,42 @@ def test_free_run_gaussian_d5_reduced(pmax):
 def test_pmax_rules_differ_only_in_searches():
     """The two P_max rules take the same decisions up to the first threshold
     search whose trajectory changes direction; after it the paper's rule
-    commits more error to finished regions, so at this tolerance (the d=5
-    Gaussian to 1e-4) it runs more searches and ends NO_ACTIVE, while the
-    memory-only rule converges."""
-    wl = W.gaussian_d5()
-    rp = oracle.integrate_workload(wl, rel_tol=1e-4, pmax_relax="paper")
-    rm = oracle.integrate_workload(wl, rel_tol=1e-4, pmax_relax="memory")
+    commits more error to finished regions. With no error kept back for the
+    active regions (budget "listing"), on the d=5 Gaussian to 1e-4 with a
+    2^16-region cap the paper's rule runs more searches and ends NO_ACTIVE,
+    while the memory-only rule converges."""
+    wl = W.gaussian_d5(max_regions=1 << 16)
+    rp = oracle.integrate_workload(wl, rel_tol=1e-4, pmax_relax="paper",
+                                   budget="listing")
+    rm = oracle.integrate_workload(wl, rel_tol=1e-4, pmax_relax="memory",
+                                   budget="listing")
     assert rm.status_name == "OK"
     assert rp.status_name == "NO_ACTIVE"
     assert rp.threshold_calls > rm.threshold_calls
     # no threshold search at all: the two rules cannot differ
     a = oracle.integrate_workload(wl, rel_tol=1e-4, threshold_filter=0,
-                                  max_regions=1 << 22, pmax_relax="paper")
+                                  pmax_relax="paper")
     b = oracle.integrate_workload(wl, rel_tol=1e-4, threshold_filter=0,
-                                  max_regions=1 << 22, pmax_relax="memory")
+                                  pmax_relax="memory")
+    assert (a.estimate, a.error, a.iterations) == (b.estimate, b.error, b.iterations)
+
+
+def test_reserve_keeps_the_run_convergent():
+    """Under the paper's P_max rule, keeping back the error the active
+    regions may still end with (Lemma 1) in searches started by the
+    settled-digits trigger keeps the finished error below tau |v|: the d=5
+    Gaussian to 1e-4 (2^16-region cap) converges with fewer searches than
+    without it, and meets its closed form."""
+    wl = W.gaussian_d5(max_regions=1 << 16)
+    wl.rel_tol = 1e-4
+    rr = oracle.integrate_workload(wl, budget="reserve")
+    rl = oracle.integrate_workload(wl, budget="listing")
+    assert rr.status_name == "OK" and rl.status_name == "NO_ACTIVE"
+    assert rr.threshold_calls < rl.threshold_calls
+    check_free_run(rr, cf.exact(wl.family, wl.params, wl.d), wl.rel_tol)
+    # without a search the budget cannot matter
+    a = oracle.integrate_workload(wl, threshold_filter=0, budget="reserve")
+    b = oracle.integrate_workload(wl, threshold_filter=0, budget="listing")
     assert (a.estimate, a.error, a.iterations) == (b.estimate, b.error, b.iterations)
 
 
