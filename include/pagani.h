@@ -416,6 +416,37 @@ int pg_filter_split(pg_context *ctx, int dim, int64_t n, const double *lo,
                     double *w_out, int64_t ld_out, double *Vp,
                     int64_t *n_active);
 
+/* ---- for callers that cannot allocate ---- */
+
+/* Largest list pg_filter_split_noalloc accepts, and the bytes of device
+   memory its scratch holds on every GPU the library runs on (from the first
+   call on that GPU until the process ends). */
+#define PG_NOALLOC_MAX_REGIONS (1LL << 26)
+#define PG_NOALLOC_SCRATCH_BYTES (5u << 20)
+
+/*
+ * pg_filter_split for callers that cannot allocate device memory: code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc. It needs no context and calls no allocating routine: the
+ * compaction's scratch (per-segment sums and counts, segment offsets,
+ * totals) is a static device array of PG_NOALLOC_SCRATCH_BYTES per GPU,
+ * whose address is looked up on the first call on each device. The caller
+ * still owns every input and output. Arguments, layouts and results are
+ * pg_filter_split's; work is queued on `stream` (a hipStream_t on the
+ * current device, NULL = its null stream) and the call blocks until
+ * *n_active is known and the output list is written. Errors (return
+ * value only; there is no context to hold a message): PG_EINVAL for
+ * n > PG_NOALLOC_MAX_REGIONS, a bad dimension, n / ld or ld_out, or a NULL
+ * array; PG_EHIP for a HIP failure. Every call on one GPU shares that GPU's
+ * scratch: calls that overlap on one GPU (other streams, other threads)
+ * race and must not be made.
+ */
+int pg_filter_split_noalloc(void *stream, int dim, int64_t n,
+                            const double *lo, const double *w, int64_t ld_in,
+                            const uint8_t *K, const double *V,
+                            const uint8_t *A, double *lo_out, double *w_out,
+                            int64_t ld_out, double *Vp, int64_t *n_active);
+
 #ifdef __cplusplus
 }
 #endif

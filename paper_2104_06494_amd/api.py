@@ -466,6 +466,35 @@ class Context:
         return lo2[:, :2 * m].contiguous(), w2[:, :2 * m].contiguous(), Vp[:m].clone()
 
 
+def filter_split_noalloc(lo, w, K, V, A, lo_out, w_out, Vp):
+    """FILTER + parent update + SPLIT into caller-allocated outputs, without a
+    context and without allocating (pg_filter_split_noalloc): lo, w are
+    [d, n] and lo_out, w_out [d, ld_out] contiguous float64 with
+    ld_out >= 2 n_active; Vp holds at least min(n, ld_out // 2) values.
+    Queued on torch's current stream. Returns n_active."""
+    lib = L.load()
+    d, n = lo.shape
+    dev = lo.device
+    for t, name in ((lo, "lo"), (w, "w"), (V, "V"), (lo_out, "lo_out"),
+                    (w_out, "w_out"), (Vp, "Vp")):
+        _check_f64(t, name, dev)
+    _check_u8(K, "K", dev)
+    _check_u8(A, "A", dev)
+    ld_out = lo_out.shape[1] if lo_out.dim() == 2 else -1
+    if w.shape != lo.shape or w_out.shape != lo_out.shape or lo_out.shape[0] != d:
+        raise ValueError("lo, w must be [d, n] and lo_out, w_out [d, ld_out]")
+    if min(V.numel(), K.numel(), A.numel()) < n or Vp.numel() < min(n, ld_out // 2):
+        raise ValueError("V, K, A need n entries and Vp min(n, ld_out // 2)")
+    na = C.c_int64()
+    with torch.cuda.device(dev):
+        rc = lib.pg_filter_split_noalloc(_stream_handle(dev), d, n, _ptr(lo), _ptr(w),
+                                         n, _ptr(K), _ptr(V), _ptr(A), _ptr(lo_out),
+                                         _ptr(w_out), ld_out, _ptr(Vp), C.byref(na))
+    if rc:
+        raise PaganiError(rc, "pg_filter_split_noalloc failed")
+    return na.value
+
+
 _default_ctx = {}
 _live = weakref.WeakSet()
 

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = [os.path.join(HERE, "csrc", s) for s in
            ("pg_evaluate.hip", "pg_list.hip", "pg_batch.hip", "pg_adjoint.hip",
-            "pg_api.hip")]
+            "pg_api.hip", "pg_noalloc.hip")]
 # the EVALUATE kernels, one object per integrand family (pg_family ids)
 FAMILY_SOURCE = os.path.join(HERE, "csrc", "pg_eval_family.hip")
 N_FAMILIES = 8
