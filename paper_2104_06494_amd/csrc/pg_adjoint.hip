@@ -130,7 +130,7 @@ __device__ __forceinline__ void region_grad(const double (&c)[D],
 #pragma unroll
             for (int k = 0; k < D; ++k) x[k] = c[k];
             const double lam = q < 2 ? R.lam2 : R.lam3;
-            x[i] = fma((q & 1) ? -1.0 : 1.0, lam * h[i], c[i]);
+            x[i] = fma((q & 1) ? -1.0 : 1.0, mul_rounded(lam, h[i]), c[i]);
             point_grad<FAM, D>(x, P, q < 2 ? wv[1] : wv[2], g);
         }
     }
@@ -143,8 +143,8 @@ __device__ __forceinline__ void region_grad(const double (&c)[D],
                 double x[D];
 #pragma unroll
                 for (int k = 0; k < D; ++k) x[k] = c[k];
-                x[i] = fma((q & 2) ? -1.0 : 1.0, R.lam4 * h[i], c[i]);
-                x[j] = fma((q & 1) ? -1.0 : 1.0, R.lam4 * h[j], c[j]);
+                x[i] = fma((q & 2) ? -1.0 : 1.0, mul_rounded(R.lam4, h[i]), c[i]);
+                x[j] = fma((q & 1) ? -1.0 : 1.0, mul_rounded(R.lam4, h[j]), c[j]);
                 point_grad<FAM, D>(x, P, wv[3], g);
             }
         }
@@ -156,7 +156,7 @@ __device__ __forceinline__ void region_grad(const double (&c)[D],
             double x[D];
 #pragma unroll
             for (int k = 0; k < D; ++k)
-                x[k] = fma(((b >> k) & 1) ? -1.0 : 1.0, R.lam5 * h[k], c[k]);
+                x[k] = fma(((b >> k) & 1) ? -1.0 : 1.0, mul_rounded(R.lam5, h[k]), c[k]);
             point_grad<FAM, D>(x, P, wv[4], g);
         }
     }

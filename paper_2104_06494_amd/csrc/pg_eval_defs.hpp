@@ -47,6 +47,16 @@ __device__ __forceinline__ double exp_nonpos(double x) {
     return ldexp(q, (int)n);
 }
 
+// a * b rounded to double by itself. HIP code is compiled with floating-
+// point contraction across statements, which would fuse a product such as
+// lambda h into the addition that uses it (c + lambda h with one rounding
+// instead of two); a cubature point's coordinate is defined as the centre
+// plus the rounded offset, so the offset's product is kept out of that.
+__device__ __forceinline__ double mul_rounded(double a, double b) {
+#pragma clang fp contract(off)
+    return a * b;
+}
+
 // 1/x for a positive x whose reciprocal is a normal number (the product
 // peak's and the corner peak's denominators, products of terms >= a^-2 and
 // >= 1): the hardware reciprocal estimate refined by two Newton-Raphson

@@ -146,8 +146,8 @@ k_evaluate(const FParams P, const Rule R, int64_t n,
     for (int k = 0; k < D; ++k) {
         h[k] = wid[k * ld + r] * 0.5;
         c[k] = lo[k * ld + r] + h[k];
-        l4[k] = R.lam4 * h[k];
-        l5[k] = R.lam5 * h[k];
+        l4[k] = mul_rounded(R.lam4, h[k]);
+        l5[k] = mul_rounded(R.lam5, h[k]);
     }
 
     double fc = 0.0;
@@ -168,7 +168,7 @@ k_evaluate(const FParams P, const Rule R, int64_t n,
 #pragma unroll
             for (int k = 0; k < D; ++k) x[k] = c[k];
             const double lam = q < 2 ? R.lam2 : R.lam3;
-            x[i] = fma((q & 1) ? -1.0 : 1.0, lam * h[i], c[i]);
+            x[i] = fma((q & 1) ? -1.0 : 1.0, mul_rounded(lam, h[i]), c[i]);
             f[q] = integrand<FAM, D>(x, PP);
         }
         const double P2 = f[0] + f[1], P3 = f[2] + f[3];
@@ -204,31 +204,32 @@ k_evaluate(const FParams P, const Rule R, int64_t n,
         int m = wave - (u0 % W);
         if (m < 0) m += W;
         if constexpr (FAM == PG_GAUSSIAN) {
-            // The Gaussian's exponent at the vertex c + sigma l5 (sigma_k =
-            // +-1) expands as S0 + sum_k sigma_k B_k with p = c - u,
-            // S0 = sum a_k^2 (p_k^2 + l5_k^2) and B_k = 2 a_k^2 p_k l5_k, so
-            // a unit of four vertices costs D - 2 FMAs for the sign choices
-            // they share and two additions each, instead of rebuilding every
-            // point. The terms are of the order of the region's spread of
-            // the exponent, so their rounding stays far inside the
-            // tolerance of the point-by-point sum.
-            double S0 = 0.0, B[D];
+            // A vertex's coordinates are, axis by axis, one of the two
+            // rounded values c_k + l5_k and c_k - l5_k (the points every
+            // other family evaluates), so the terms a_k^2 (x_k - u_k)^2 of
+            // its exponent are computed once per axis and sign; a unit of
+            // four vertices then costs D - 2 additions for the sign choices
+            // they share and two each. The terms are nonnegative, so their
+            // sum rounds like the point-by-point one (relative error of a
+            // few ulps, no cancellation).
+            double qp[D], qm[D];
 #pragma unroll
             for (int k = 0; k < D; ++k) {
-                const double pk = c[k] - PP.p[D + k];
-                S0 = fma(PP.p[k], fma(pk, pk, l5[k] * l5[k]), S0);
-                B[k] = (2.0 * PP.p[k] * pk) * l5[k];
+                const double tp = fma(1.0, l5[k], c[k]) - PP.p[D + k];
+                const double tm = fma(-1.0, l5[k], c[k]) - PP.p[D + k];
+                qp[k] = (PP.p[k] * tp) * tp;
+                qm[k] = (PP.p[k] * tm) * tm;
             }
             for (; m < N5; m += W) {
-                double base = S0;
+                double base = 0.0;
 #pragma unroll
                 for (int k = 2; k < D; ++k)
-                    base = fma((((4 * m) >> k) & 1) ? -1.0 : 1.0, B[k], base);
+                    base += (((4 * m) >> k) & 1) ? qm[k] : qp[k];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const double s0 = (q & 1) ? base - B[0] : base + B[0];
-                    const double sv = (q & 2) ? s0 - B[1] : s0 + B[1];
-                    S5 += exp_nonpos(-sv);
+                    const double s01 = ((q & 1) ? qm[0] : qp[0]) +
+                                       ((q & 2) ? qm[1] : qp[1]);
+                    S5 += exp_nonpos(-(s01 + base));
                 }
             }
         } else {

@@ -138,6 +138,38 @@ def test_evaluate_parity_one_wave_per_block(ctx, family, d, n):
     assert_region_parity(ref, lo, w, V.cpu().numpy(), E.cpu().numpy(), K.cpu().numpy())
 
 
+VERTEX_CASES = [(d, a, g) for d in (5, 8) for a in (10.0, 1e3, 3e4)
+                for g in (0.5, 3.0, 10.0, 30.0)]
+
+
+@pytest.mark.parametrize("d,a_scale,g", VERTEX_CASES)
+def test_gaussian_vertex_points_at_extremes(ctx, d, a_scale, g):
+    """The Gaussian at its sharpest (a up to 3e4, the documented limit) on
+    boxes whose vertex points lie g Gaussian widths from the centre along
+    every axis (lambda5 a h = g), half of them with a vertex exactly on the
+    peak u. Exponents reach hundreds, so f = e^-s magnifies any difference
+    in how a point's coordinates round: an ulp in x_k moves s by
+    2 a^2 t_k ulp(x_k), about 1e-12 of f here (the size of the difference a
+    fused c + lambda h, one rounding instead of two, made). Per-region
+    parity with the oracle's point-by-point values to the usual bound
+    (1e-12 relative plus the oracle's rounding floor)."""
+    _say("vertex-extremes", d, a_scale, g)
+    rng = np.random.default_rng(int(d * 1000 + g))
+    n = 512
+    a = a_scale * rng.uniform(0.5, 1.5, size=d)
+    u = rng.uniform(0.3, 0.7, size=d)
+    lam5 = np.sqrt(9.0 / 19.0)
+    h = g / (lam5 * a[:, None]) * rng.uniform(0.8, 1.25, size=(d, n))
+    c = u[:, None] + h * lam5 * rng.choice([-1.0, 1.0], size=(d, n))
+    c[:, n // 2:] += h[:, n // 2:] * rng.uniform(-0.5, 0.5, size=(d, n - n // 2))
+    lo, w = c - h, 2.0 * h
+    p = np.concatenate([a, u])
+    V, E, K = ctx.evaluate("gaussian", p, _dev(lo), _dev(w))
+    torch.cuda.synchronize()
+    ref = oracle.eval_regions("gaussian", d, p, lo, w)
+    assert_region_parity(ref, lo, w, V.cpu().numpy(), E.cpu().numpy(), K.cpu().numpy())
+
+
 def test_evaluate_strided_rows(ctx):
     """Rows of lo/w taken from a wider buffer (leading dimension > n)."""
     d, n, ld = 4, 300, 512
