@@ -40,15 +40,16 @@ sys.path.insert(0, ROOT)
 
 # FP64 operations of one evaluation of an integrand, counted with rocprofv3
 # ((ADD + MUL + TRANS + 2 FMA)_F64 per evaluation) on the integrand-only
-# kernel (--mode integrand); see profiles/evaluate_gaussian_d5_counters.txt.
+# kernel (--mode integrand); see profiles/integrand_flops.txt.
 # Algorithmic FLOP per region = N points x (F + 1 orbit accumulation).
-F_FLOP = {("gaussian", 5): 47.0}
+F_FLOP = {("gaussian", 5): 47.0, ("product_peak", 3): 20.0, ("oscillatory", 8): 73.0,
+          ("corner_peak", 6): 27.0}
 # HBM bytes per evaluate launch of this workload from FETCH_SIZE / WRITE_SIZE
 # (scaled by a plain copy), valid only for the kernel source they were taken
 # on (first 16 hex digits of the sha256 of pg_eval_kernels.hpp followed by
 # pg_eval_defs.hpp, comments and blank space removed); reported as null
 # otherwise.
-EVAL_TRAFFIC = {"bytes_per_launch": 37759311.2, "kernel_sha256": "ca1f2b37fe775935",
+EVAL_TRAFFIC = {"bytes_per_launch": 39318016.0, "kernel_sha256": "90774d6067e4cb1e",
                 "profile": "profiles/evaluate_gaussian_d5_counters.txt"}
 # MI355X FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz.
 PEAK_FP64_TFLOPS = 78.6
@@ -286,6 +287,8 @@ def batched(args):
     B = min(wl.B, args.batch_count) if args.batch_count else wl.B
     slots = args.batch_slots
     with pg.Context(capacity=slots * wl.max_regions, dim_max=wl.d) as ctx:
+        if args.eval_waves:
+            ctx.set_eval_waves(args.eval_waves)
         ctx.integrate_batch_workload(wl, count=min(B, 2 * slots))
         rb, tb, tbs = _median_runs(lambda: ctx.integrate_batch_workload(wl, count=B),
                                    args.reps)
@@ -503,6 +506,19 @@ def _errors_sweep(args, ctx):
                     "ms": ms}), flush=True)
 
 
+def autotune_mode(args):
+    """The autotuner over the corner-peak batch: EVALUATE's wave target x
+    integrals in flight, median of --reps runs each, and the fastest."""
+    import torch
+    import workloads as W
+    from paper_2104_06494_amd import autotune
+    torch.cuda.set_device(0)
+    wl = W.corner_peak_batch_d6()
+    out = autotune.tune_batched(wl, count=args.batch_count or None, reps=args.reps)
+    print(json.dumps({"mode": "autotune", "workload": "corner_peak_batch_d6", **out}),
+          flush=True)
+
+
 def batched_mode(args):
     """The batched comparison alone (for profiling)."""
     print(json.dumps({"mode": "batched", **batched(args)}), flush=True)
@@ -574,7 +590,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--mode", choices=["headline", "batched", "adjoint", "suite",
-                                       "errors", "integrand", "copy"],
+                                       "errors", "integrand", "copy", "autotune"],
                     default="headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-configs", action="store_true",
@@ -611,6 +627,9 @@ def main():
     ap.add_argument("--adjoint-count", type=int, default=0,
                     help="first parameter points only (0 = all 256)")
     ap.add_argument("--adjoint-error-rule", default="raw", choices=["raw", "null4"])
+    ap.add_argument("--eval-waves", type=int, default=0,
+                    help="EVALUATE's wave target in the batched run (0: the "
+                         "library's default)")
     ap.add_argument("--batch-slots", type=int, default=64,
                     help="integrals in flight in the batched run (each "
                          "reserves 2^21 regions of workspace)")
@@ -622,7 +641,7 @@ def main():
         sys.exit(2)
     {"headline": headline, "batched": batched_mode, "adjoint": adjoint_mode,
      "suite": suite_mode, "errors": errors_mode, "integrand": integrand_mode,
-     "copy": copy_mode}[args.mode](args)
+     "copy": copy_mode, "autotune": autotune_mode}[args.mode](args)
 
 
 if __name__ == "__main__":

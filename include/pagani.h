@@ -224,6 +224,14 @@ int pg_context_create(int device, int dim_max, int64_t capacity,
 void pg_context_destroy(pg_context *ctx);
 /* Replace the stream work is queued on (a hipStream_t, NULL = null stream). */
 int pg_context_set_stream(pg_context *ctx, void *stream);
+/* Waves EVALUATE (Section 3.2) aims to keep in flight on this context's
+   runs: blocks x waves per block, the waves of a block splitting the rule's
+   points of its 64 regions. 0 restores the default, 2048 (the chip twice
+   over); PG_EINVAL outside 256..65536. Meant to change speed only: the
+   waves' partial sums are added in another order, so estimates move by
+   rounding and a decision on an exact rounding tie could go the other way.
+   Set by the autotuner of the many-integral driver. */
+int pg_context_set_eval_waves(pg_context *ctx, int target);
 /* Message of the last error on this context ("" if none). */
 const char *pg_last_error(const pg_context *ctx);
 

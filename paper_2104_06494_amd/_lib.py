@@ -33,7 +33,7 @@ EXPORTS = ["pg_default_options", "pg_workspace_bytes", "pg_context_create",
            "pg_integrate", "pg_last_regions", "pg_evaluate", "pg_classify",
            "pg_threshold_search", "pg_filter_split", "pg_integrand_values",
            "pg_integrate_batch", "pg_integrate_grad", "pg_integrate_batch_grad",
-           "pg_evaluate_rule", "pg_filter_split_noalloc"]
+           "pg_evaluate_rule", "pg_filter_split_noalloc", "pg_context_set_eval_waves"]
 
 
 class Integrand(C.Structure):
@@ -145,5 +145,7 @@ def load():
     L.pg_filter_split_noalloc.argtypes = [vp, C.c_int, i64, vp, vp, i64, vp, vp, vp,
                                           vp, vp, i64, vp, C.POINTER(i64)]
     L.pg_filter_split_noalloc.restype = C.c_int
+    L.pg_context_set_eval_waves.argtypes = [vp, C.c_int]
+    L.pg_context_set_eval_waves.restype = C.c_int
     _lib = L
     return L

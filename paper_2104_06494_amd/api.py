@@ -146,6 +146,13 @@ class Context:
     def __exit__(self, *a):
         self.close()
 
+    def set_eval_waves(self, target: int = 0):
+        """Waves EVALUATE aims to keep in flight (0: the default, 2048);
+        changes the order of the waves' partial sums, not the rule."""
+        rc = self.lib.pg_context_set_eval_waves(self.h, int(target))
+        if rc:
+            raise self._err(rc)
+
     # -- helpers ----------------------------------------------------------
     def _bind_stream(self):
         self.lib.pg_context_set_stream(self.h, _stream_handle(self.device))

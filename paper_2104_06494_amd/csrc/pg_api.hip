@@ -17,6 +17,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -24,9 +25,14 @@
 
 using namespace pg;
 
+// Waves in flight EVALUATE aims for by default: the chip twice over (256
+// CUs x 4 SIMDs x 2).
+constexpr int64_t EVAL_WAVE_TARGET = 2048;
+
 struct pg_context {
     int device = 0;
     hipStream_t stream = nullptr;            // nullptr: the null stream
+    int64_t wave_target = EVAL_WAVE_TARGET;  // EVALUATE's waves in flight
     int dim_max = 0;
     int64_t cap = 0;
     void *ws = nullptr;
@@ -52,13 +58,17 @@ struct pg_context {
     uint64_t seq = 0;
     // many-integral runs
     uint32_t *inst[2] = {nullptr, nullptr};
-    BInst *b_inst = nullptr, *hb_inst = nullptr;
+    // the slot header of a many-integral run, one device block (per run:
+    // slot table, order, new-slot list, search states, in that order) and
+    // its pinned staging copies, so that each upload is one copy
+    char *b_hdr = nullptr, *hb_hdr = nullptr;
+    BInst *b_inst = nullptr;
     SearchState *b_state = nullptr, *hb_state = nullptr;
     Totals *b_tot = nullptr, *hb_tot = nullptr;
     Totals *hb_tot_dev = nullptr;            // device address of hb_tot
     FParams *b_table = nullptr, *hb_table = nullptr;
     int32_t *b_order = nullptr, *hb_order = nullptr;
-    int32_t *b_new = nullptr, *hb_new = nullptr;
+    int32_t *b_new = nullptr, *hb_new = nullptr;   // hb_*: host values
     BSeg *b_segs = nullptr;
     BCls *b_cls = nullptr;
     double *b_tpart = nullptr;
@@ -83,14 +93,34 @@ struct pg_context {
 namespace {
 
 constexpr size_t ALIGN = 256;
-// Pinned staging copies of the slot table, used in turn (a copy is reused
+// Pinned staging copies of the slot header, used in turn (a copy is reused
 // only after a stream synchronisation has passed since its last upload).
 constexpr int INST_STAGES = 4;
+
+// Offsets in the slot header of a run with K slots: slot table, order,
+// new-slot list, search states. An upload copies the prefix up to the end
+// of the last part it needs, in one copy.
+constexpr size_t hdr_round(size_t x) { return (x + 255) / 256 * 256; }
+struct HdrLayout {
+    size_t order, nw, state, end_inst, end_order, end_new, end_state;
+};
+constexpr HdrLayout hdr_layout(size_t K) {
+    HdrLayout h{};
+    h.end_inst = sizeof(BInst) * K;
+    h.order = hdr_round(h.end_inst);
+    h.end_order = h.order + sizeof(int32_t) * K;
+    h.nw = hdr_round(h.end_order);
+    h.end_new = h.nw + sizeof(int32_t) * K;
+    h.state = hdr_round(h.end_new);
+    h.end_state = h.state + sizeof(SearchState) * K;
+    return h;
+}
+constexpr size_t HDR_MAX = hdr_round(hdr_layout(BATCH_MAX_SLOTS).end_state);
 
 struct Layout {
     size_t lo[2], w[2], V, E, Vp, K, A, A2;
     size_t pv, pe, pav, pae, pfv, pmin, pmax, pcnt, off;
-    size_t inst[2], b_inst, b_state, b_tot, b_table, b_order, b_new, b_segs,
+    size_t inst[2], b_hdr, b_tot, b_table, b_segs,
         b_cls, b_tpart, b_gtable, b_gpart, b_git, hcnt, hsum, htlo, hthi;
     size_t search_part, dtot, dstate, total;
     int64_t nseg;
@@ -132,12 +162,9 @@ Layout layout(int dim_max, int64_t cap) {
     L.off = bump(at, sizeof(uint32_t) * L.nseg);
     L.search_part = bump(at, sizeof(double) * 2 * TRIAL_M * TRIAL_BLOCKS);
     for (int q = 0; q < 2; ++q) L.inst[q] = bump(at, sizeof(uint32_t) * cap);
-    L.b_inst = bump(at, sizeof(BInst) * BATCH_MAX_SLOTS);
-    L.b_state = bump(at, sizeof(SearchState) * BATCH_MAX_SLOTS);
+    L.b_hdr = bump(at, HDR_MAX);
     L.b_tot = bump(at, sizeof(Totals) * BATCH_MAX_SLOTS);
     L.b_table = bump(at, sizeof(FParams) * BATCH_MAX_SLOTS);
-    L.b_order = bump(at, sizeof(int32_t) * BATCH_MAX_SLOTS);
-    L.b_new = bump(at, sizeof(int32_t) * BATCH_MAX_SLOTS);
     L.b_segs = bump(at, sizeof(BSeg) * L.nseg);
     L.b_cls = bump(at, sizeof(BCls) * L.nseg);
     L.b_tpart = bump(at, sizeof(double) * 2 * TRIAL_M * L.nseg);
@@ -400,11 +427,10 @@ void make_gparams(int family, int d, const double *p, GParams *G) {
     }
 }
 
-// Waves per evaluation block: enough blocks x waves to cover the chip twice
-// over (256 CUs x 4 SIMDs x 2), at most the number of work units allows.
-int eval_waves(int d, int64_t n) {
+// Waves per evaluation block: enough blocks x waves to reach `target`
+// waves, at most the number of work units allows.
+int eval_waves(int d, int64_t n, int64_t target) {
     const int64_t blocks = (n + 63) / 64;
-    const int64_t target = 2048;
     int w = 1;
     const int wmax = evaluate_max_waves(d);
     while (w < wmax && blocks * w < target) w *= 2;
@@ -655,9 +681,8 @@ int pg_context_create(int device, int dim_max, int64_t capacity,
             hipSuccess ||
         hipHostGetDevicePointer((void **)&ctx->hseq_dev, ctx->hseq, 0) !=
             hipSuccess ||
-        hipHostMalloc((void **)&ctx->hb_inst,
-                      sizeof(BInst) * INST_STAGES * BATCH_MAX_SLOTS,
-                      0) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->hb_hdr, HDR_MAX * INST_STAGES, 0) !=
+            hipSuccess ||
         hipHostMalloc((void **)&ctx->hb_gtable,
                       sizeof(GParams) * BATCH_MAX_SLOTS, 0) != hipSuccess ||
         hipHostMalloc((void **)&ctx->hb_git,
@@ -672,10 +697,8 @@ int pg_context_create(int device, int dim_max, int64_t capacity,
             hipSuccess ||
         hipHostMalloc((void **)&ctx->hb_table,
                       sizeof(FParams) * BATCH_MAX_SLOTS, 0) != hipSuccess ||
-        hipHostMalloc((void **)&ctx->hb_order,
-                      sizeof(int32_t) * BATCH_MAX_SLOTS, 0) != hipSuccess ||
-        hipHostMalloc((void **)&ctx->hb_new, sizeof(int32_t) * BATCH_MAX_SLOTS,
-                      0) != hipSuccess) {
+        !(ctx->hb_order = new (std::nothrow) int32_t[BATCH_MAX_SLOTS]) ||
+        !(ctx->hb_new = new (std::nothrow) int32_t[BATCH_MAX_SLOTS])) {
         pg_context_destroy(ctx);
         return PG_ENOMEM;
     }
@@ -702,12 +725,9 @@ int pg_context_create(int device, int dim_max, int64_t capacity,
     ctx->off = (uint32_t *)(b + L.off);
     ctx->search_part = (double *)(b + L.search_part);
     for (int q = 0; q < 2; ++q) ctx->inst[q] = (uint32_t *)(b + L.inst[q]);
-    ctx->b_inst = (BInst *)(b + L.b_inst);
-    ctx->b_state = (SearchState *)(b + L.b_state);
+    ctx->b_hdr = b + L.b_hdr;
     ctx->b_tot = (Totals *)(b + L.b_tot);
     ctx->b_table = (FParams *)(b + L.b_table);
-    ctx->b_order = (int32_t *)(b + L.b_order);
-    ctx->b_new = (int32_t *)(b + L.b_new);
     ctx->b_segs = (BSeg *)(b + L.b_segs);
     ctx->b_cls = (BCls *)(b + L.b_cls);
     ctx->b_tpart = (double *)(b + L.b_tpart);
@@ -738,10 +758,12 @@ void pg_context_destroy(pg_context *ctx) {
     if (ctx->htot) (void)hipHostFree(ctx->htot);
     if (ctx->hstate) (void)hipHostFree(ctx->hstate);
     if (ctx->hseq) (void)hipHostFree(ctx->hseq);
-    void *pinned[] = {ctx->hb_inst, ctx->hb_state, ctx->hb_tot, ctx->hb_table,
-                      ctx->hb_order, ctx->hb_new, ctx->hb_gtable, ctx->hb_git};
+    void *pinned[] = {ctx->hb_hdr, ctx->hb_state, ctx->hb_tot, ctx->hb_table,
+                      ctx->hb_gtable, ctx->hb_git};
     for (void *q : pinned)
         if (q) (void)hipHostFree(q);
+    delete[] ctx->hb_order;
+    delete[] ctx->hb_new;
     if (ctx->own_ws && ctx->ws) (void)hipFree(ctx->ws);
     delete ctx;
 }
@@ -749,6 +771,15 @@ void pg_context_destroy(pg_context *ctx) {
 int pg_context_set_stream(pg_context *ctx, void *stream) {
     if (!ctx) return PG_EINVAL;
     ctx->stream = (hipStream_t)stream;
+    return PG_OK;
+}
+
+int pg_context_set_eval_waves(pg_context *ctx, int target) {
+    if (!ctx) return PG_EINVAL;
+    if (target == 0) target = (int)EVAL_WAVE_TARGET;
+    if (target < 256 || target > 65536)
+        return fail(ctx, PG_EINVAL, "wave target %d outside 256..65536", target);
+    ctx->wave_target = target;
     return PG_OK;
 }
 
@@ -779,7 +810,7 @@ int pg_evaluate_rule(pg_context *ctx, const pg_integrand *f, int error_rule,
     const Rule R = make_rule(f->dim, error_rule);
     HIP_OR_FAIL(ctx, launch_evaluate(ctx->stream, f->family, f->dim, P, R, n,
                                      lo, w, ld, V, E, K,
-                                     eval_waves(f->dim, n)));
+                                     eval_waves(f->dim, n, ctx->wave_target)));
     return PG_OK;
 }
 
@@ -1019,7 +1050,7 @@ int pg_integrate(pg_context *ctx, const pg_integrand *f, const double *lo,
         if (timing) RUN_FAIL(hipEventRecord(ev[0], st));
         RUN_FAIL(launch_evaluate(st, f->family, d, P, R, n, ctx->lo[cur],
                                  ctx->w[cur], ld, ctx->V, ctx->E, ctx->K,
-                                 eval_waves(d, n)));
+                                 eval_waves(d, n, ctx->wave_target)));
         ++nev;
         if (timing) RUN_FAIL(hipEventRecord(ev[1], st));
         res.regions_evaluated += n;
@@ -1308,11 +1339,31 @@ static int run_batch(pg_context *ctx, int family, int dim, int B,
             running += g_d;
         }
     };
-    auto upload_inst = [&]() -> int {
-        BInst *h = ctx->hb_inst + (size_t)stage * BATCH_MAX_SLOTS;
+    // the slot header: one upload of the prefix a phase needs
+    const HdrLayout hl = hdr_layout((size_t)K);
+    ctx->b_inst = (BInst *)ctx->b_hdr;
+    ctx->b_order = (int32_t *)(ctx->b_hdr + hl.order);
+    ctx->b_new = (int32_t *)(ctx->b_hdr + hl.nw);
+    ctx->b_state = (SearchState *)(ctx->b_hdr + hl.state);
+    enum { UP_INST, UP_ORDER, UP_NEW, UP_STATE };
+    auto upload = [&](int upto) -> int {
+        char *h = ctx->hb_hdr + (size_t)stage * HDR_MAX;
         stage = (stage + 1) % INST_STAGES;
         std::memcpy(h, HI, sizeof(BInst) * K);
-        HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->b_inst, h, sizeof(BInst) * K,
+        size_t bytes = hl.end_inst;
+        if (upto >= UP_ORDER) {
+            std::memcpy(h + hl.order, ctx->hb_order, sizeof(int32_t) * K);
+            bytes = hl.end_order;
+        }
+        if (upto >= UP_NEW) {
+            std::memcpy(h + hl.nw, ctx->hb_new, sizeof(int32_t) * K);
+            bytes = hl.end_new;
+        }
+        if (upto >= UP_STATE) {
+            std::memcpy(h + hl.state, ctx->hb_state, sizeof(SearchState) * K);
+            bytes = hl.end_state;
+        }
+        HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->b_hdr, h, bytes,
                                         hipMemcpyHostToDevice, st));
         return PG_OK;
     };
@@ -1331,10 +1382,7 @@ static int run_batch(pg_context *ctx, int family, int dim, int B,
             HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->b_gtable, ctx->hb_gtable,
                                             sizeof(GParams) * K,
                                             hipMemcpyHostToDevice, st));
-        HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->b_new, ctx->hb_new,
-                                        sizeof(int32_t) * nnew,
-                                        hipMemcpyHostToDevice, st));
-        BRUN(upload_inst());
+        BRUN(upload(UP_NEW));
         HIP_OR_FAIL(ctx, launch_batch_init(st, d, o.init_splits, a, width, nnew,
                                            ctx->b_new, ctx->b_inst,
                                            ctx->lo[cur], ctx->w[cur], ld,
@@ -1377,14 +1425,12 @@ static int run_batch(pg_context *ctx, int family, int dim, int B,
         const int64_t nseg = seg0, ncls = cls0;
         if (nseg > ctx->nseg_max)
             return fail(ctx, PG_ENOMEM, "segment table overflow");
-        BRUN(upload_inst());
-        HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->b_order, ctx->hb_order,
-                                        sizeof(int32_t) * nslots,
-                                        hipMemcpyHostToDevice, st));
+        BRUN(upload(UP_ORDER));
         // ---- EVALUATE, TWO-LEVEL + CLASSIFY, per-slot sums
         HIP_OR_FAIL(ctx, launch_evaluate(st, family, d, dummy, R, n_total,
                                          ctx->lo[cur], ctx->w[cur], ld, ctx->V,
-                                         ctx->E, ctx->K, eval_waves(d, n_total),
+                                         ctx->E, ctx->K,
+                                         eval_waves(d, n_total, ctx->wave_target),
                                          ctx->inst[cur], ctx->b_table));
         HIP_OR_FAIL(ctx, launch_batch_tables(st, nslots, ctx->b_order,
                                              ctx->b_inst, ctx->b_segs,
@@ -1434,12 +1480,9 @@ static int run_batch(pg_context *ctx, int family, int dim, int B,
                 ++searching;
             }
         }
-        BRUN(upload_inst());
+        BRUN(upload(searching ? UP_STATE : UP_INST));
         // ---- THRESHOLD-CLASSIFY for every slot that needs it
         if (searching) {
-            HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->b_state, ctx->hb_state,
-                                            sizeof(SearchState) * K,
-                                            hipMemcpyHostToDevice, st));
             const int max_passes =
                 (THR_MAX_TRIALS + TRIAL_DEPTH - 1) / TRIAL_DEPTH;
             HIP_OR_FAIL(ctx, launch_batch_search_hist(
@@ -1466,15 +1509,11 @@ static int run_batch(pg_context *ctx, int family, int dim, int B,
                     if (HI[k].searching && !ctx->hb_state[k].done) all = false;
                 if (all) break;
             }
-            for (int k : order) {
-                if (!HI[k].searching) continue;
-                SearchState &z = ctx->hb_state[k];
-                if (!z.done) z.ok = 0;                 // trial limit reached
-                out[slots[k].b].threshold_trials += z.trials;
-            }
-            HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->b_state, ctx->hb_state,
-                                            sizeof(SearchState) * K,
-                                            hipMemcpyHostToDevice, st));
+            // a search that has not ended has not accepted (ok is set only
+            // with done), so the device's states need no correction
+            for (int k : order)
+                if (HI[k].searching)
+                    out[slots[k].b].threshold_trials += ctx->hb_state[k].trials;
         }
         // ---- survivors per slot
         HIP_OR_FAIL(ctx, launch_batch_count(st, nseg, ctx->b_segs, ctx->b_inst,
@@ -1535,7 +1574,7 @@ static int run_batch(pg_context *ctx, int family, int dim, int B,
             if (leaves && n_leaves + fin > leaves->ld)
                 return fail(ctx, PG_ENOMEM, "more than %lld leaves",
                             (long long)leaves->ld);
-            BRUN(upload_inst());
+            BRUN(upload(UP_INST));
             LeafOut lout{};
             if (leaves) {
                 lout.lo = leaves->lo;
@@ -1560,7 +1599,7 @@ static int run_batch(pg_context *ctx, int family, int dim, int B,
         }
         order.swap(next_order);
         admit();
-        BRUN(upload_inst());
+        BRUN(upload(nnew ? UP_NEW : UP_INST));
         HIP_OR_FAIL(ctx, launch_batch_compact(
                              st, d, nseg, ctx->b_segs, ctx->b_inst,
                              ctx->b_state, ctx->A, ctx->E, ctx->V, ctx->K,
@@ -1575,9 +1614,6 @@ static int run_batch(pg_context *ctx, int family, int dim, int B,
                 HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->b_gtable, ctx->hb_gtable,
                                                 sizeof(GParams) * K,
                                                 hipMemcpyHostToDevice, st));
-            HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->b_new, ctx->hb_new,
-                                            sizeof(int32_t) * nnew,
-                                            hipMemcpyHostToDevice, st));
             HIP_OR_FAIL(ctx, launch_batch_init(st, d, o.init_splits, a, width,
                                                nnew, ctx->b_new, ctx->b_inst,
                                                ctx->lo[1 - cur], ctx->w[1 - cur],

@@ -63,9 +63,9 @@ k_batch_reduce(const int32_t *__restrict__ order,
                Totals *__restrict__ host_tot) {
     const int slot = order[blockIdx.x];
     const BInst &I = inst[slot];
-    reduce_scan_segments(I.seg0, I.nseg, part, offsets, tot + slot);
+    const Totals t = reduce_scan_segments(I.seg0, I.nseg, part, offsets, tot + slot);
     // the host's copy (mapped pinned host memory), when given
-    if (host_tot && threadIdx.x == 0) host_tot[slot] = tot[slot];
+    if (host_tot && threadIdx.x == 0) host_tot[slot] = t;
 }
 
 // Threshold trials of every searching slot: block per segment, the sums of

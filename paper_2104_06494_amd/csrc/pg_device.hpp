@@ -185,10 +185,10 @@ __device__ inline void count_segment(int64_t s0, int64_t s1, int mode,
 // Totals of the segment partials [seg0, seg0 + nseg) and the exclusive scan
 // of their counts (one block of SCAN_THREADS threads).
 // ---------------------------------------------------------------------------
-__device__ inline void reduce_scan_segments(int64_t seg0, int64_t nseg,
-                                            SegPartials part,
-                                            uint32_t *__restrict__ offsets,
-                                            Totals *__restrict__ tot) {
+__device__ inline Totals reduce_scan_segments(int64_t seg0, int64_t nseg,
+                                              SegPartials part,
+                                              uint32_t *__restrict__ offsets,
+                                              Totals *__restrict__ tot) {
     __shared__ uint64_t wsum[SCAN_THREADS / 64];
     __shared__ Acc wacc[SCAN_THREADS / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -228,20 +228,23 @@ __device__ inline void reduce_scan_segments(int64_t seg0, int64_t nseg,
     for (int off = 32; off >= 1; off >>= 1) a.shfl_merge(off);
     if (lane == 0) wacc[wave] = a;
     __syncthreads();
+    Totals r{};
     if (tid == 0) {
         Acc t = wacc[0];
         for (int q = 1; q < SCAN_THREADS / 64; ++q) t.merge(wacc[q]);
         uint64_t total = 0;
         for (int q = 0; q < SCAN_THREADS / 64; ++q) total += wsum[q];
-        tot->v = t.v;
-        tot->e = t.e;
-        tot->av = t.av;
-        tot->ae = t.ae;
-        tot->emin = t.mn;
-        tot->emax = t.mx;
-        tot->cnt = (double)total;
-        tot->fv = t.fv;
+        r.v = t.v;
+        r.e = t.e;
+        r.av = t.av;
+        r.ae = t.ae;
+        r.emin = t.mn;
+        r.emax = t.mx;
+        r.cnt = (double)total;
+        r.fv = t.fv;
+        *tot = r;
     }
+    return r;          // the totals (thread 0 only)
 }
 
 // ---------------------------------------------------------------------------

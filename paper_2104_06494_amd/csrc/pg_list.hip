@@ -56,11 +56,12 @@ k_reduce_scan(int64_t nseg, SegPartials part, uint32_t *__restrict__ offsets,
               const SearchState *__restrict__ state,
               SearchState *__restrict__ host_state, uint64_t *host_seq,
               uint64_t seq) {
-    reduce_scan_segments(0, nseg, part, offsets, tot);
+    const Totals t = reduce_scan_segments(0, nseg, part, offsets, tot);
     // the host's copies (pinned host memory mapped into the device's
-    // address space), so that no copy has to be queued behind this kernel
+    // address space), so that no copy has to be queued behind this kernel;
+    // the totals straight from registers
     if (threadIdx.x == 0) {
-        if (host_tot) *host_tot = *tot;
+        if (host_tot) *host_tot = t;
         if (host_state) *host_state = *state;
         // then the sequence number the host polls for: once it reads `seq`
         // there, the copies above are visible to it as well

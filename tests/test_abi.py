@@ -80,3 +80,9 @@ def test_product_path_has_no_cpu_fallback():
         if fn.endswith(".py"):
             src = open(os.path.join(pkg, fn)).read()
             assert "oracle" not in src, fn
+
+
+def test_eval_wave_target_needs_a_context():
+    from paper_2104_06494_amd import _lib
+    lib = _lib.load()
+    assert lib.pg_context_set_eval_waves(None, 2048) == -1

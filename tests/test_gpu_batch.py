@@ -187,6 +187,24 @@ def test_batch_headline_sample():
     ctx.close()
 
 
+def test_eval_wave_target_changes_speed_only():
+    """EVALUATE's wave target (the autotuner's knob) changes how a region's
+    points are shared among waves, so estimates move by the order of sums,
+    but every integral takes the same decisions."""
+    _say("eval-wave-target")
+    wl = _small_corner_batch(12, seed=47)
+    ctx = _ctx(12 * wl.max_regions, wl.d)
+    ref = ctx.integrate_batch_workload(wl)
+    for target in (256, 16384, 0):
+        ctx.set_eval_waves(target)
+        res = ctx.integrate_batch_workload(wl)
+        for b, (r, q) in enumerate(zip(res, ref)):
+            _assert_same_run(r, q, b)
+    with pytest.raises(Exception):
+        ctx.set_eval_waves(100)
+    ctx.close()
+
+
 def test_batch_bitwise_reproducible():
     _say("batch-determinism")
     wl = _small_corner_batch(8, seed=45)
