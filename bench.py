@@ -43,7 +43,10 @@ sys.path.insert(0, ROOT)
 # kernel (--mode integrand); see profiles/integrand_flops.txt.
 # Algorithmic FLOP per region = N points x (F + 1 orbit accumulation).
 F_FLOP = {("gaussian", 5): 47.0, ("product_peak", 3): 20.0, ("oscillatory", 8): 73.0,
-          ("corner_peak", 6): 27.0}
+          ("corner_peak", 6): 27.0,
+          # not measured: the d=5 Gaussian's counts plus one more axis (one
+          # subtraction, one multiply, one FMA)
+          ("gaussian", 6): 51.0}
 # HBM bytes per evaluate launch of this workload from FETCH_SIZE / WRITE_SIZE
 # (scaled by a plain copy), valid only for the kernel source they were taken
 # on (first 16 hex digits of the sha256 of pg_eval_kernels.hpp followed by
@@ -349,7 +352,7 @@ def adjoint(args):
     if args.adjoint_cap:
         wl.max_regions = args.adjoint_cap
     B = min(wl.B, args.adjoint_count) if args.adjoint_count else wl.B
-    slots = max(1, min(args.batch_slots // 2, (1 << 27) // wl.max_regions))
+    slots = max(1, min(args.batch_slots // 2, args.adjoint_capacity // wl.max_regions))
     kw = dict(error_rule=args.adjoint_error_rule)
     with pg.Context(capacity=slots * wl.max_regions, dim_max=wl.d) as ctx:
         ctx.integrate_batch_workload(wl, count=min(B, slots), grad=True, **kw)
@@ -370,6 +373,17 @@ def adjoint(args):
             gerr.append(_grad_scaled_error(G[b], ref, I, wl.params[b], wl.d) / tau)
         gerr = np.array(gerr)
         ok = np.array([r.status_name == "OK" for r in rg])
+        # The derivative pass evaluates the integrand and its 2d parameter
+        # derivatives at every point of each final partition. Every
+        # evaluated region is either a leaf of that partition or was split
+        # into two evaluated children, so leaves = (evaluated + initial)/2.
+        # Work per point: F_f + 1 for the value and its weight, 4 per
+        # parameter (derivative factor, product with f, weight, sum).
+        init = wl.init_splits ** wl.d
+        leaves = sum((r.regions_evaluated + init) // 2 for r in rg)
+        pts = leaves * (2 ** wl.d + 2 * wl.d * wl.d + 2 * wl.d + 1)
+        adj_flop = pts * (F_FLOP[("gaussian", wl.d)] + 1 + 4 * 2 * wl.d)
+        adj_s = max(tg - tf, 1e-9)
         out = {"workload": "gaussian_grad_d6", "B": B, "slots_in_flight": slots,
                "rel_tol": float(wl.rel_tol[0]), "max_regions": wl.max_regions,
                "error_rule": args.adjoint_error_rule,
@@ -386,7 +400,15 @@ def adjoint(args):
                    "median": float(np.median(gerr)), "max": float(gerr.max()),
                    "max_converged": float(gerr[ok].max()) if ok.any() else None,
                    "within_1": int((gerr <= 1).sum()),
-                   "within_10": int((gerr <= 10).sum())}}
+                   "within_10": int((gerr <= 10).sum())},
+               "adjoint_roofline": {
+                   "bound": "alu", "achieved": adj_flop / adj_s / 1e12,
+                   "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                   "frac": adj_flop / adj_s / 1e12 / PEAK_FP64_TFLOPS,
+                   "leaves": int(leaves), "points": int(pts),
+                   "flop_per_point": F_FLOP[("gaussian", wl.d)] + 1 + 8 * wl.d,
+                   "time": "forward+derivative wall time minus forward wall "
+                           "time (includes the derivative reduction and its copies)"}}
         if not args.no_plain:
             t0 = time.perf_counter()
             for b in range(B):
@@ -626,6 +648,10 @@ def main():
                          "(0: the workload's 2^22)")
     ap.add_argument("--adjoint-count", type=int, default=0,
                     help="first parameter points only (0 = all 256)")
+    ap.add_argument("--adjoint-capacity", type=int, default=1 << 27,
+                    help="regions of the derivative run's context (integrals "
+                         "in flight: this / the cap, at most half of "
+                         "--batch-slots)")
     ap.add_argument("--adjoint-error-rule", default="raw", choices=["raw", "null4"])
     ap.add_argument("--eval-waves", type=int, default=0,
                     help="EVALUATE's wave target in the batched run (0: the "
