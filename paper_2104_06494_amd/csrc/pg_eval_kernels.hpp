@@ -129,7 +129,8 @@ k_evaluate(const FParams P, const Rule R, int64_t n,
     // the wave index is the same on every lane: say so, so that the unit
     // loop, the point signs and the pair decoding stay in scalar registers
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int W = blockDim.x >> 6;
+    const int W = blockDim.x >> 6;           // 1, 2, 4 or 8 (launch_evaluate)
+    const int wmask = W - 1;                 // unit u goes to wave u mod W
     const int64_t r0 = (int64_t)blockIdx.x * 64 + lane;
     const int64_t r = r0 < n ? r0 : n - 1;   // tail lanes recompute the last
 
@@ -160,7 +161,7 @@ k_evaluate(const FParams P, const Rule R, int64_t n,
     // coordinate is recomputed (unit u = i goes to wave u mod W)
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-        if (i % W != wave) continue;
+        if ((i & wmask) != wave) continue;
         double f[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -174,9 +175,13 @@ k_evaluate(const FParams P, const Rule R, int64_t n,
         const double P2 = f[0] + f[1], P3 = f[2] + f[3];
         S2 += P2;
         S3 += P3;
-        Dbuf[i * 64 + lane] = fabs((P2 - 2.0 * fc) - (P3 - 2.0 * fc) / 7.0);
+        // lambda2^2 / lambda3^2 = 1/7, as a product by RN(1/7): a division
+        // costs ten instructions, and the split axis is chosen with a
+        // relative tie margin far above this rounding
+        constexpr double SEVENTH = 1.0 / 7.0;
+        Dbuf[i * 64 + lane] = fabs((P2 - 2.0 * fc) - (P3 - 2.0 * fc) * SEVENTH);
         const double nm = (fabs(f[0]) + fabs(f[1])) +
-                          (fabs(f[2]) + fabs(f[3])) / 7.0 +
+                          (fabs(f[2]) + fabs(f[3])) * SEVENTH +
                           (12.0 / 7.0) * fabs(fc);
         nmax = fmax(nmax, nm);
     }
@@ -186,7 +191,7 @@ k_evaluate(const FParams P, const Rule R, int64_t n,
 #pragma unroll
         for (int j = i + 1; j < D; ++j) {
             const int u = D + i * (2 * D - i - 1) / 2 + (j - i - 1);
-            if (u % W != wave) continue;
+            if ((u & wmask) != wave) continue;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 double x[D];
@@ -201,7 +206,7 @@ k_evaluate(const FParams P, const Rule R, int64_t n,
     // vertex units
     {
         int u0 = D + NPAIR;
-        int m = wave - (u0 % W);
+        int m = wave - (u0 & wmask);
         if (m < 0) m += W;
         if constexpr (FAM == PG_GAUSSIAN) {
             // A vertex's coordinates are, axis by axis, one of the two
@@ -220,17 +225,26 @@ k_evaluate(const FParams P, const Rule R, int64_t n,
                 qp[k] = (PP.p[k] * tp) * tp;
                 qm[k] = (PP.p[k] * tm) * tm;
             }
-            for (; m < N5; m += W) {
+            auto unit = [&](int mm) {
                 double base = 0.0;
 #pragma unroll
                 for (int k = 2; k < D; ++k)
-                    base += (((4 * m) >> k) & 1) ? qm[k] : qp[k];
+                    base += (((4 * mm) >> k) & 1) ? qm[k] : qp[k];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const double s01 = ((q & 1) ? qm[0] : qp[0]) +
                                        ((q & 2) ? qm[1] : qp[1]);
                     S5 += exp_nonpos(-(s01 + base));
                 }
+            };
+            if constexpr (N5 <= 16) {
+                // unrolled: the unit's signs are compile-time, so its terms
+                // are picked without selects (up to d = 6)
+#pragma unroll
+                for (int mm = 0; mm < N5; ++mm)
+                    if (((u0 + mm) & wmask) == wave) unit(mm);
+            } else {
+                for (; m < N5; m += W) unit(m);
             }
         } else {
             for (; m < N5; m += W) {

@@ -75,6 +75,9 @@ hipError_t launch_evaluate(hipStream_t st, int family, int d,
     EvalKernel k = eval_kernel(family, d, inst != nullptr);
     if (!k) return hipErrorInvalidValue;
     if (n <= 0) return hipSuccess;
+    // the kernel assigns work units to waves by u mod W with a bit mask
+    if (waves < 1 || waves > EVAL_MAX_WAVES || (waves & (waves - 1)))
+        return hipErrorInvalidValue;
     const int64_t blocks = (n + 63) / 64;
     const size_t lds = sizeof(double) * 64 * (size_t)(d + (waves > 1 ? 5 * waves : 0));
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * waves), lds, st, P,
