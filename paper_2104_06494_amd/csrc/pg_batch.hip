@@ -198,9 +198,15 @@ k_batch_count(const BSeg *__restrict__ segs, const BInst *__restrict__ inst,
 // values at Vp[s / 2 + k] (k-th survivor), which is where the classify pass
 // of the next iteration looks for them; blocks of 2 na regions give
 // disjoint parent ranges whatever the parity of s.
-__global__ void __launch_bounds__(LIST_THREADS)
-k_batch_compact(int d, const BSeg *__restrict__ segs,
-                const BInst *__restrict__ inst,
+// Twice the list kernels' threads, so that a BSEG-long segment takes four
+// regions a thread (two load-then-store steps, as in the single list's
+// compaction), and the dimension a template argument, so that a thread's
+// two boxes take 4 D registers (two blocks a CU up to D = 6).
+constexpr int BCOMPACT_THREADS = 2 * LIST_THREADS;
+
+template <int D>
+__global__ void __launch_bounds__(BCOMPACT_THREADS)
+k_batch_compact(const BSeg *__restrict__ segs, const BInst *__restrict__ inst,
                 const SearchState *__restrict__ states,
                 const uint8_t *__restrict__ A_rel, const double *__restrict__ E,
                 const double *__restrict__ V, const uint8_t *__restrict__ K,
@@ -212,10 +218,10 @@ k_batch_compact(int d, const BSeg *__restrict__ segs,
     const BInst &I = inst[sg.slot];
     const int mode = batch_mode(I, states[sg.slot]);
     if (mode == 0) return;
-    compact_segment<BSEG>(d, sg.start, sg.end, mode, states[sg.slot].t_acc, A_rel, E,
-                    V, K, lo, w, ld, I.out_start + offsets[blockIdx.x], I.na,
-                    lo_out, w_out, ld, Vp, I.out_start - I.out_start / 2,
-                    inst_out, sg.slot);
+    compact_segment<BSEG, BCOMPACT_THREADS, D>(
+        D, sg.start, sg.end, mode, states[sg.slot].t_acc, A_rel, E, V, K, lo,
+        w, ld, I.out_start + offsets[blockIdx.x], I.na, lo_out, w_out, ld, Vp,
+        I.out_start - I.out_start / 2, inst_out, sg.slot);
 }
 
 struct BatchBox {
@@ -329,9 +335,23 @@ hipError_t launch_batch_compact(hipStream_t st, int d, int64_t nseg,
                                 double *w_out, double *Vp,
                                 uint32_t *inst_out) {
     if (nseg <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_compact, dim3((unsigned)nseg), dim3(LIST_THREADS),
-                       0, st, d, segs, inst, states, A_rel, E, V, K, lo, w, ld,
-                       offsets, lo_out, w_out, Vp, inst_out);
+    static_assert(PG_DIM_MIN == 2 && PG_DIM_MAX == 10, "one kernel per dimension");
+    decltype(&k_batch_compact<2>) k = nullptr;
+    switch (d) {
+    case 2: k = k_batch_compact<2>; break;
+    case 3: k = k_batch_compact<3>; break;
+    case 4: k = k_batch_compact<4>; break;
+    case 5: k = k_batch_compact<5>; break;
+    case 6: k = k_batch_compact<6>; break;
+    case 7: k = k_batch_compact<7>; break;
+    case 8: k = k_batch_compact<8>; break;
+    case 9: k = k_batch_compact<9>; break;
+    case 10: k = k_batch_compact<10>; break;
+    default: return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(k, dim3((unsigned)nseg), dim3(BCOMPACT_THREADS), 0, st,
+                       segs, inst, states, A_rel, E, V, K, lo, w, ld, offsets,
+                       lo_out, w_out, Vp, inst_out);
     return hipGetLastError();
 }
 

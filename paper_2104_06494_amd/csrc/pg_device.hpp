@@ -573,15 +573,16 @@ __device__ inline void sum_trial_parts(const double *__restrict__ src,
 
 // ---------------------------------------------------------------------------
 // FILTER + parent update + SPLIT of one segment [s0, s1) of at most SEGLEN
-// regions by one block: the flags of all SEGLEN / LIST_THREADS rounds are
-// read first (region
-// s0 + r * LIST_THREADS + tid in round r, coalesced), their wave ballots give
-// the prefix in (round, wave) order after one barrier, and the survivors are
-// then copied and bisected: the survivor at output index j = base + prefix
-// goes to j (lower half) and j + na (upper half), with Vp[j - vp_shift] = V.
-// With a non-null inst_out, the children are tagged with `tag`.
+// regions by one block of NT threads: the flags of all SEGLEN / NT rounds
+// are read first (region s0 + r * NT + tid in round r, coalesced), their
+// wave ballots give the prefix in (round, wave) order after one barrier,
+// and the survivors are then copied and bisected: the survivor at output
+// index j = base + prefix goes to j (lower half) and j + na (upper half),
+// with Vp[j - vp_shift] = V. With a non-null inst_out, the children are
+// tagged with `tag`. DC > 0 fixes the dimension at compile time (d is then
+// ignored), so a box takes exactly DC registers per coordinate array.
 // ---------------------------------------------------------------------------
-template <int SEGLEN>
+template <int SEGLEN, int NT = LIST_THREADS, int DC = 0>
 __device__ inline void compact_segment(
     int d, int64_t s0, int64_t s1, int mode, double t,
     const uint8_t *__restrict__ A_rel, const double *__restrict__ E,
@@ -590,16 +591,18 @@ __device__ inline void compact_segment(
     int64_t ld_in, int64_t base, int64_t na, double *__restrict__ lo_out,
     double *__restrict__ w_out, int64_t ld_out, double *__restrict__ Vp,
     int64_t vp_shift, uint32_t *__restrict__ inst_out, uint32_t tag) {
-    constexpr int CS_ROUNDS = SEGLEN / LIST_THREADS;
+    constexpr int CS_ROUNDS = SEGLEN / NT;
+    constexpr int DA = DC > 0 ? DC : PG_DIM_MAX;   // coordinate registers
+    if constexpr (DC > 0) d = DC;
     static_assert(CS_ROUNDS % 2 == 0, "compaction pairs rounds");
-    constexpr int NW = LIST_THREADS / 64;
+    constexpr int NW = NT / 64;
     __shared__ uint32_t wcnt[CS_ROUNDS * NW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint64_t below = (1ull << lane) - 1ull;
     uint32_t act = 0, pre[CS_ROUNDS];
 #pragma unroll
     for (int r = 0; r < CS_ROUNDS; ++r) {
-        const int64_t i = s0 + r * LIST_THREADS + threadIdx.x;
+        const int64_t i = s0 + r * NT + threadIdx.x;
         const bool a = i < s1 && mode != 0 && A_rel[i] &&
                        (mode == 1 || E[i] > t);
         const uint64_t mask = __ballot(a);
@@ -626,16 +629,16 @@ __device__ inline void compact_segment(
     // written, so a thread has two rounds of loads in flight
 #pragma unroll
     for (int r0 = 0; r0 < CS_ROUNDS; r0 += 2) {
-        double l[2][PG_DIM_MAX], ww[2][PG_DIM_MAX], v[2];
+        double l[2][DA], ww[2][DA], v[2];
         int ax[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             if (!((act >> (r0 + h)) & 1u)) continue;
-            const int64_t i = s0 + (r0 + h) * LIST_THREADS + threadIdx.x;
+            const int64_t i = s0 + (r0 + h) * NT + threadIdx.x;
             ax[h] = K[i];
             v[h] = V[i];
 #pragma unroll
-            for (int k = 0; k < PG_DIM_MAX; ++k) {
+            for (int k = 0; k < DA; ++k) {
                 if (k < d) {
                     l[h][k] = lo[k * ld_in + i];
                     ww[h][k] = w[k * ld_in + i];
@@ -647,7 +650,7 @@ __device__ inline void compact_segment(
             if (!((act >> (r0 + h)) & 1u)) continue;
             const int64_t j = dst[r0 + h];
 #pragma unroll
-            for (int k = 0; k < PG_DIM_MAX; ++k) {
+            for (int k = 0; k < DA; ++k) {
                 if (k < d) {
                     const double half = ww[h][k] * 0.5;
                     const bool sp = k == ax[h];

@@ -211,9 +211,11 @@ k_trial_walk(int nblk, const double *__restrict__ blk_part,
 }
 
 // FILTER + parent update + SPLIT: block b compacts segment b; its base is
-// the exclusive scan of the segment counts.
+// the exclusive scan of the segment counts. The dimension is a template
+// argument, so a thread's two boxes take 4 D registers.
+template <int D>
 __global__ void __launch_bounds__(LIST_THREADS)
-k_compact_split(int d, int64_t n, int paired, double t,
+k_compact_split(int64_t n, int paired, double t,
                 const uint8_t *__restrict__ A_rel, const double *__restrict__ E,
                 const double *__restrict__ V, const uint8_t *__restrict__ K,
                 const double *__restrict__ lo, const double *__restrict__ w,
@@ -223,9 +225,10 @@ k_compact_split(int d, int64_t n, int paired, double t,
                 double *__restrict__ Vp) {
     int64_t s0, s1;
     seg_range(blockIdx.x, n, paired, &s0, &s1);
-    compact_segment<SEG>(d, s0, s1, E ? 2 : 1, t, A_rel, E, V, K, lo, w, ld_in,
-                    offsets[blockIdx.x], na, lo_out, w_out, ld_out, Vp, 0,
-                    nullptr, 0);
+    compact_segment<SEG, LIST_THREADS, D>(D, s0, s1, E ? 2 : 1, t, A_rel, E, V,
+                                          K, lo, w, ld_in, offsets[blockIdx.x],
+                                          na, lo_out, w_out, ld_out, Vp, 0,
+                                          nullptr, 0);
 }
 
 __global__ void k_apply_threshold(int64_t n, double t,
@@ -365,8 +368,22 @@ hipError_t launch_compact_split(hipStream_t st, int d, int64_t n, int paired,
                                 double *lo_out, double *w_out, int64_t ld_out,
                                 double *Vp) {
     if (n <= 0 || n_active <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_compact_split, dim3((unsigned)seg_count(n, paired)),
-                       dim3(LIST_THREADS), 0, st, d, n, paired, t, A_rel, E, V,
+    static_assert(PG_DIM_MIN == 2 && PG_DIM_MAX == 10, "one kernel per dimension");
+    decltype(&k_compact_split<2>) k = nullptr;
+    switch (d) {
+    case 2: k = k_compact_split<2>; break;
+    case 3: k = k_compact_split<3>; break;
+    case 4: k = k_compact_split<4>; break;
+    case 5: k = k_compact_split<5>; break;
+    case 6: k = k_compact_split<6>; break;
+    case 7: k = k_compact_split<7>; break;
+    case 8: k = k_compact_split<8>; break;
+    case 9: k = k_compact_split<9>; break;
+    case 10: k = k_compact_split<10>; break;
+    default: return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(k, dim3((unsigned)seg_count(n, paired)),
+                       dim3(LIST_THREADS), 0, st, n, paired, t, A_rel, E, V,
                        K, lo, w, ld_in, offsets, n_active, lo_out, w_out,
                        ld_out, Vp);
     return hipGetLastError();
