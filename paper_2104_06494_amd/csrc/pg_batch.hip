@@ -11,17 +11,17 @@
 
 namespace pg {
 
-// Expands the segment table and the classify items of every live slot (one
-// thread per slot, slots in list order).
-__global__ void k_batch_tables(int nslots, const int32_t *__restrict__ order,
-                               const BInst *__restrict__ inst,
-                               BSeg *__restrict__ segs, BCls *__restrict__ cls) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nslots) return;
-    const uint32_t slot = (uint32_t)order[k];
+// Expands the segment table and the classify items of every live slot: one
+// block per slot (slots in list order), its threads striding over the
+// slot's segments.
+__global__ void __launch_bounds__(256)
+k_batch_tables(const int32_t *__restrict__ order,
+               const BInst *__restrict__ inst, BSeg *__restrict__ segs,
+               BCls *__restrict__ cls) {
+    const uint32_t slot = (uint32_t)order[blockIdx.x];
     const BInst I = inst[slot];
     if (!I.paired) {
-        for (int64_t j = 0; j < I.nseg; ++j) {
+        for (int64_t j = threadIdx.x; j < I.nseg; j += blockDim.x) {
             const int64_t s0 = I.start + j * BSEG;
             const int64_t s1 = s0 + BSEG < I.start + I.n ? s0 + BSEG : I.start + I.n;
             segs[I.seg0 + j] = BSeg{s0, s1, slot, 0};
@@ -31,7 +31,7 @@ __global__ void k_batch_tables(int nslots, const int32_t *__restrict__ order,
     }
     const int64_t half = I.n / 2;
     const int64_t nh = (half + BSEG - 1) / BSEG;
-    for (int64_t j = 0; j < nh; ++j) {
+    for (int64_t j = threadIdx.x; j < nh; j += blockDim.x) {
         const int64_t q0 = j * BSEG, q1 = q0 + BSEG < half ? q0 + BSEG : half;
         segs[I.seg0 + j] = BSeg{I.start + q0, I.start + q1, slot, 0};
         segs[I.seg0 + nh + j] = BSeg{I.start + half + q0, I.start + half + q1,
@@ -257,8 +257,8 @@ __global__ void k_batch_init(int d, int g, int64_t n, const BatchBox B,
 hipError_t launch_batch_tables(hipStream_t st, int nslots, const int32_t *order,
                                const BInst *inst, BSeg *segs, BCls *cls) {
     if (nslots <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_tables, dim3((nslots + 255) / 256), dim3(256), 0,
-                       st, nslots, order, inst, segs, cls);
+    hipLaunchKernelGGL(k_batch_tables, dim3((unsigned)nslots), dim3(256), 0,
+                       st, order, inst, segs, cls);
     return hipGetLastError();
 }
 
