@@ -56,7 +56,7 @@ k_batch_classify(const BCls *__restrict__ cls, const BInst *__restrict__ inst,
 
 // Per-slot totals of its segment partials and the exclusive scan of their
 // counts (offsets within the slot), one block per slot.
-__global__ void __launch_bounds__(SCAN_THREADS)
+__global__ void __launch_bounds__(REDUCE_THREADS)
 k_batch_reduce(const int32_t *__restrict__ order,
                const BInst *__restrict__ inst, SegPartials part,
                uint32_t *__restrict__ offsets, Totals *__restrict__ tot,
@@ -277,7 +277,7 @@ hipError_t launch_batch_reduce(hipStream_t st, int nslots,
                                SegPartials part, uint32_t *offsets,
                                Totals *tot, Totals *host_tot) {
     if (nslots <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_reduce, dim3(nslots), dim3(SCAN_THREADS), 0, st,
+    hipLaunchKernelGGL(k_batch_reduce, dim3(nslots), dim3(REDUCE_THREADS), 0, st,
                        order, inst, part, offsets, tot, host_tot);
     return hipGetLastError();
 }

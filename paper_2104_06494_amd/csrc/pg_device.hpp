@@ -183,16 +183,17 @@ __device__ inline void count_segment(int64_t s0, int64_t s1, int mode,
 
 // ---------------------------------------------------------------------------
 // Totals of the segment partials [seg0, seg0 + nseg) and the exclusive scan
-// of their counts (one block of SCAN_THREADS threads).
+// of their counts (one block of NT threads).
 // ---------------------------------------------------------------------------
+template <int NT = REDUCE_THREADS>
 __device__ inline Totals reduce_scan_segments(int64_t seg0, int64_t nseg,
                                               SegPartials part,
                                               uint32_t *__restrict__ offsets,
                                               Totals *__restrict__ tot) {
-    __shared__ uint64_t wsum[SCAN_THREADS / 64];
-    __shared__ Acc wacc[SCAN_THREADS / 64];
+    __shared__ uint64_t wsum[NT / 64];
+    __shared__ Acc wacc[NT / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t per = (nseg + SCAN_THREADS - 1) / SCAN_THREADS;
+    const int64_t per = (nseg + NT - 1) / NT;
     const int64_t s0 = seg0 + tid * per;
     const int64_t s1 = s0 + per < seg0 + nseg ? s0 + per : seg0 + nseg;
     Acc a;
@@ -231,9 +232,9 @@ __device__ inline Totals reduce_scan_segments(int64_t seg0, int64_t nseg,
     Totals r{};
     if (tid == 0) {
         Acc t = wacc[0];
-        for (int q = 1; q < SCAN_THREADS / 64; ++q) t.merge(wacc[q]);
+        for (int q = 1; q < NT / 64; ++q) t.merge(wacc[q]);
         uint64_t total = 0;
-        for (int q = 0; q < SCAN_THREADS / 64; ++q) total += wsum[q];
+        for (int q = 0; q < NT / 64; ++q) total += wsum[q];
         r.v = t.v;
         r.e = t.e;
         r.av = t.av;

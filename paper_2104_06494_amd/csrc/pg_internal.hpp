@@ -28,8 +28,13 @@ constexpr int TRIAL_THREADS = 1024;
 // search's possible next steps.
 constexpr int TRIAL_DEPTH = 4;
 constexpr int TRIAL_M = (1 << TRIAL_DEPTH) - 1;
-// Threads of the single-block reduce/scan kernels.
+// Threads of the single-block walk kernels (at least 32 TRIAL_M: the trial
+// sums take 16 threads each).
 constexpr int SCAN_THREADS = 1024;
+// Threads of a block reducing segment partials (single list: one block;
+// many integrals: one per slot). A list has at most a few thousand
+// segments, and fewer waves shorten the block's barrier and merge.
+constexpr int REDUCE_THREADS = 256;
 
 
 // Segment geometry of a list of n regions (paired: two halves of n/2).

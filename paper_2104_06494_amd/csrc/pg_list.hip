@@ -50,7 +50,7 @@ k_seg_count(int64_t n, int paired, double t, const double *__restrict__ V,
 }
 
 // Single-block totals of the segment partials + exclusive scan of the counts
-__global__ void __launch_bounds__(SCAN_THREADS)
+__global__ void __launch_bounds__(REDUCE_THREADS)
 k_reduce_scan(int64_t nseg, SegPartials part, uint32_t *__restrict__ offsets,
               Totals *__restrict__ tot, Totals *__restrict__ host_tot,
               const SearchState *__restrict__ state,
@@ -309,7 +309,7 @@ hipError_t launch_reduce_scan(hipStream_t st, int64_t nseg, SegPartials part,
                               const SearchState *state,
                               SearchState *host_state, uint64_t *host_seq,
                               uint64_t seq) {
-    hipLaunchKernelGGL(k_reduce_scan, dim3(1), dim3(SCAN_THREADS), 0, st, nseg,
+    hipLaunchKernelGGL(k_reduce_scan, dim3(1), dim3(REDUCE_THREADS), 0, st, nseg,
                        part, offsets, tot, host_tot, state, host_state,
                        host_seq, seq);
     return hipGetLastError();
