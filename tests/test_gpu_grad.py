@@ -103,9 +103,14 @@ def test_grad_against_differences_on_the_frozen_partition(ctx, family, d, tol, r
 
 def test_gaussian_d6_gradient_meets_the_closed_form(ctx):
     """The d=6 Gaussian parameter points at their tolerance (1e-5): the
-    estimate meets it against the erf closed form, and the derivative,
-    whose accuracy the run does not control, lies within 100 tau of the
-    closed-form gradient (relative to its largest component)."""
+    estimate meets it against the erf closed form, and each component of
+    the derivative lies within tau of the closed form's on the component's
+    own scale, |dI/dtheta_k| + |I| / s_k with s_k = a_k for a_k and 1 / a_k
+    for u_k (the size a change of theta_k by its own width moves I by).
+    The run controls the estimate's error, not the derivative's; on that
+    scale the derivative's error measures at most 0.64 tau over all 256
+    points of the workload at 1e-5 (and 0.095 tau for the converged ones
+    at 1e-7), so tau is the bound asserted."""
     _say("grad-closed-form gaussian d6")
     wl = W.gaussian_grad_d6(B=6)
     n_ok = 0
@@ -120,7 +125,9 @@ def test_gaussian_d6_gradient_meets_the_closed_form(ctx):
         I, dA, dU = cf.gaussian_grad(p, 6)
         ref = np.concatenate([dA, dU])
         assert abs(r.estimate - I) <= tau * abs(I)
-        np.testing.assert_allclose(g, ref, rtol=0, atol=100 * tau * np.max(np.abs(ref)))
+        a = p[:6]
+        scale = np.abs(ref) + abs(I) / np.concatenate([a, 1.0 / a])
+        assert np.all(np.abs(g - ref) <= tau * scale), np.max(np.abs(g - ref) / scale) / tau
     assert n_ok >= wl.B - 1
 
 
