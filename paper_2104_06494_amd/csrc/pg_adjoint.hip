@@ -98,11 +98,7 @@ __device__ __forceinline__ void point_grad(const double (&x)[D],
         double s = 1.0;
 #pragma unroll
         for (int k = 0; k < D; ++k) s = fma(P.p[k], x[k], s);
-        const double r = rcp_pos(s);
-        double f = r;
-#pragma unroll
-        for (int k = 1; k < D + 2; ++k) f *= r;
-        const double wf = wgt * f;
+        const double wf = wgt * pow_int<D + 2>(rcp_pos(s));
 #pragma unroll
         for (int k = 0; k < D; ++k) g[k] = fma(x[k], wf, g[k]);
     }

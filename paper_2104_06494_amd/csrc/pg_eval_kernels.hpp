@@ -51,10 +51,7 @@ __device__ __forceinline__ double integrand(const double *x, const FParams &P) {
         double s = 1.0;
 #pragma unroll
         for (int k = 0; k < D; ++k) s = fma(P.p[k], x[k], s);
-        double pw = s;
-#pragma unroll
-        for (int e = 0; e < D; ++e) pw *= s;   // s^(D+1)
-        return rcp_pos(pw);
+        return rcp_pos(pow_int<D + 1>(s));
     } else if constexpr (FAM == PG_MONOMIAL) {   // test family
         double r = 1.0;
 #pragma unroll
