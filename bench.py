@@ -52,7 +52,7 @@ F_FLOP = {("gaussian", 5): 47.0, ("product_peak", 3): 20.0, ("oscillatory", 8): 
 # on (first 16 hex digits of the sha256 of pg_eval_kernels.hpp followed by
 # pg_eval_defs.hpp, comments and blank space removed); reported as null
 # otherwise.
-EVAL_TRAFFIC = {"bytes_per_launch": 39377310.5, "kernel_sha256": "08e276cebfa52b47",
+EVAL_TRAFFIC = {"bytes_per_launch": 39379407.2, "kernel_sha256": "5e52acb6786c2b51",
                 "profile": "profiles/evaluate_gaussian_d5_counters.txt"}
 # MI355X FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz.
 PEAK_FP64_TFLOPS = 78.6

@@ -205,33 +205,60 @@ k_evaluate(const FParams P, const Rule R, int64_t n,
         int u0 = D + NPAIR;
         int m = wave - (u0 & wmask);
         if (m < 0) m += W;
-        if constexpr (FAM == PG_GAUSSIAN) {
-            // A vertex's coordinates are, axis by axis, one of the two
-            // rounded values c_k + l5_k and c_k - l5_k (the points every
-            // other family evaluates), so the terms a_k^2 (x_k - u_k)^2 of
-            // its exponent are computed once per axis and sign; a unit of
-            // four vertices then costs D - 2 additions for the sign choices
-            // they share and two each. The terms are nonnegative, so their
-            // sum rounds like the point-by-point one (relative error of a
-            // few ulps, no cancellation).
+        // The families below are functions of per-axis terms combined by
+        // one operation: the Gaussian of the sum of a_k^2 (x_k - u_k)^2,
+        // the corner peak and the oscillatory of the sum of a_k x_k, the
+        // product peak of the product of a_k^-2 + (x_k - u_k)^2. A vertex's
+        // coordinates are, axis by axis, one of the two rounded values
+        // c_k + l5_k and c_k - l5_k (the points every other family
+        // evaluates), so its terms are computed once per axis and sign; a
+        // unit of four vertices then combines D - 2 terms it shares and two
+        // of its own per vertex. The rounding differs from the point-by-
+        // point form only in the order the terms are combined (a few ulps;
+        // the Gaussian's and the peaks' terms are positive, so nothing
+        // cancels).
+        constexpr bool SEP = FAM == PG_GAUSSIAN || FAM == PG_CORNER_PEAK ||
+                             FAM == PG_OSCILLATORY || FAM == PG_PRODUCT_PEAK;
+        constexpr bool PROD = FAM == PG_PRODUCT_PEAK;
+        if constexpr (SEP) {
             double qp[D], qm[D];
 #pragma unroll
             for (int k = 0; k < D; ++k) {
-                const double tp = fma(1.0, l5[k], c[k]) - PP.p[D + k];
-                const double tm = fma(-1.0, l5[k], c[k]) - PP.p[D + k];
-                qp[k] = (PP.p[k] * tp) * tp;
-                qm[k] = (PP.p[k] * tm) * tm;
+                const double xp = fma(1.0, l5[k], c[k]);
+                const double xm = fma(-1.0, l5[k], c[k]);
+                if constexpr (FAM == PG_GAUSSIAN) {
+                    const double tp = xp - PP.p[D + k], tm = xm - PP.p[D + k];
+                    qp[k] = (PP.p[k] * tp) * tp;
+                    qm[k] = (PP.p[k] * tm) * tm;
+                } else if constexpr (FAM == PG_PRODUCT_PEAK) {
+                    const double tp = xp - PP.p[D + k], tm = xm - PP.p[D + k];
+                    qp[k] = fma(tp, tp, PP.p[k]);
+                    qm[k] = fma(tm, tm, PP.p[k]);
+                } else {
+                    qp[k] = PP.p[k] * xp;
+                    qm[k] = PP.p[k] * xm;
+                }
             }
+            auto join = [](double x, double y) { return PROD ? x * y : x + y; };
+            auto value = [&](double t) {
+                if constexpr (FAM == PG_GAUSSIAN) return exp_nonpos(-t);
+                else if constexpr (FAM == PG_CORNER_PEAK)
+                    return rcp_pos(pow_int<D + 1>(1.0 + t));
+                else if constexpr (FAM == PG_OSCILLATORY) return cos(PP.p[D] + t);
+                else return rcp_pos(t);
+            };
             auto unit = [&](int mm) {
-                double base = 0.0;
+                double base = PROD ? 1.0 : 0.0;
 #pragma unroll
-                for (int k = 2; k < D; ++k)
-                    base += (((4 * mm) >> k) & 1) ? qm[k] : qp[k];
+                for (int k = 2; k < D; ++k) {
+                    const double q = (((4 * mm) >> k) & 1) ? qm[k] : qp[k];
+                    base = k == 2 ? q : join(base, q);
+                }
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const double s01 = ((q & 1) ? qm[0] : qp[0]) +
-                                       ((q & 2) ? qm[1] : qp[1]);
-                    S5 += exp_nonpos(-(s01 + base));
+                    const double s01 = join((q & 1) ? qm[0] : qp[0],
+                                            (q & 2) ? qm[1] : qp[1]);
+                    S5 += value(D > 2 ? join(s01, base) : s01);
                 }
             };
             if constexpr (N5 <= 16) {
