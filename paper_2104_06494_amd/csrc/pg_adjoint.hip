@@ -52,25 +52,37 @@ constexpr int n_grad() {
 //             df/da_k = -(x_k sin phi),     df/du_1 = -2 pi (sin phi)
 //   corner    f = s^-(d+1), s = 1 + sum a x:
 //             df/da_k = -(d+1) (x_k s^-(d+2))
+// The Gaussian's point term from t_k = x_k - u_k: f = e^-s, s the sum of
+// (a_k t_k)^2; d/du_k = 2 a_k^2 t_k f and d/da_k = -2 a_k t_k^2 f, whose
+// constant factors gs are applied once per integral.
+template <int D>
+__device__ __forceinline__ void gauss_grad_t(const double (&t)[D],
+                                             const GParams &P, double wgt,
+                                             double *g) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const double at = P.p[k] * t[k];
+        s = fma(at, at, s);
+    }
+    const double wf = wgt * exp_nonpos(-s);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const double wt = wf * t[k];
+        g[D + k] += wt;
+        g[k] = fma(wt, t[k], g[k]);
+    }
+}
+
 template <int FAM, int D>
 __device__ __forceinline__ void point_grad(const double (&x)[D],
                                            const GParams &P, double wgt,
                                            double *g) {
     if constexpr (FAM == PG_GAUSSIAN) {
-        double t[D], s = 0.0;
+        double t[D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-            t[k] = x[k] - P.p[D + k];
-            const double at = P.p[k] * t[k];
-            s = fma(at, at, s);
-        }
-        const double wf = wgt * exp_nonpos(-s);
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            const double wt = wf * t[k];
-            g[D + k] += wt;
-            g[k] = fma(wt, t[k], g[k]);
-        }
+        for (int k = 0; k < D; ++k) t[k] = x[k] - P.p[D + k];
+        gauss_grad_t<D>(t, P, wgt, g);
     } else if constexpr (FAM == PG_PRODUCT_PEAK) {
         double t[D], r[D], f = 1.0;
 #pragma unroll
@@ -145,15 +157,36 @@ __device__ __forceinline__ void region_grad(const double (&c)[D],
             }
         }
     }
-    for (int m = 0; m < (1 << D) / 4; ++m) {
-#pragma unroll 2
-        for (int q = 0; q < 4; ++q) {
-            const int b = 4 * m + q;
-            double x[D];
+    if constexpr (FAM == PG_GAUSSIAN && D <= 6) {
+        // t_k at the two vertex coordinates of each axis, once per region;
+        // the vertices, unrolled, pick theirs at compile time (same values
+        // and order of sums as the point-by-point walk below)
+        double tp[D], tm[D];
 #pragma unroll
-            for (int k = 0; k < D; ++k)
-                x[k] = fma(((b >> k) & 1) ? -1.0 : 1.0, mul_rounded(R.lam5, h[k]), c[k]);
-            point_grad<FAM, D>(x, P, wv[4], g);
+        for (int k = 0; k < D; ++k) {
+            const double l5 = mul_rounded(R.lam5, h[k]);
+            tp[k] = fma(1.0, l5, c[k]) - P.p[D + k];
+            tm[k] = fma(-1.0, l5, c[k]) - P.p[D + k];
+        }
+#pragma unroll
+        for (int b = 0; b < (1 << D); ++b) {
+            double t[D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) t[k] = ((b >> k) & 1) ? tm[k] : tp[k];
+            gauss_grad_t<D>(t, P, wv[4], g);
+        }
+    } else {
+        for (int m = 0; m < (1 << D) / 4; ++m) {
+#pragma unroll 2
+            for (int q = 0; q < 4; ++q) {
+                const int b = 4 * m + q;
+                double x[D];
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+                    x[k] = fma(((b >> k) & 1) ? -1.0 : 1.0,
+                               mul_rounded(R.lam5, h[k]), c[k]);
+                point_grad<FAM, D>(x, P, wv[4], g);
+            }
         }
     }
 }
