@@ -125,16 +125,34 @@ k_batch_trials(const BSeg *__restrict__ segs, int64_t nseg,
 
 // Error histograms of every searching slot (block per segment), then the
 // trials they decide (block per slot).
+// Segment-table entries one histogram block takes (see k_batch_hist).
+constexpr int BHIST_SEGS = HIST_RANGE / BSEG;
+static_assert(BHIST_SEGS >= 1, "histogram block range");
+
 __global__ void __launch_bounds__(LIST_THREADS)
-k_batch_hist(const BSeg *__restrict__ segs, const BInst *__restrict__ inst,
+k_batch_hist(const BSeg *__restrict__ segs, int64_t nseg,
+             const BInst *__restrict__ inst,
              const SearchState *__restrict__ states,
              const double *__restrict__ E, const uint8_t *__restrict__ A_rel,
              uint32_t *__restrict__ cnt, unsigned long long *__restrict__ sum) {
-    const BSeg sg = segs[blockIdx.x];
-    if (!inst[sg.slot].searching || states[sg.slot].done) return;
-    hist_segment(sg.start, sg.end, E, A_rel, hist_key(states[sg.slot].mx),
-                 cnt + (size_t)sg.slot * HIST_BINS,
-                 sum + (size_t)sg.slot * HIST_BINS);
+    // BHIST_SEGS consecutive table entries a block; a slot's entries cover
+    // consecutive regions (lower halves, then upper halves), so each run of
+    // one slot is one range of at most HIST_RANGE regions, and a slot's
+    // histogram receives a quarter of the flushes it would with a block
+    // per segment
+    const int64_t a0 = (int64_t)blockIdx.x * BHIST_SEGS;
+    const int64_t a1 = a0 + BHIST_SEGS < nseg ? a0 + BHIST_SEGS : nseg;
+    for (int64_t a = a0; a < a1;) {
+        const uint32_t slot = segs[a].slot;
+        int64_t b = a + 1;
+        while (b < a1 && segs[b].slot == slot) ++b;
+        if (inst[slot].searching && !states[slot].done)
+            hist_segment(segs[a].start, segs[b - 1].end, E, A_rel,
+                         hist_key(states[slot].mx),
+                         cnt + (size_t)slot * HIST_BINS,
+                         sum + (size_t)slot * HIST_BINS);
+        a = b;
+    }
 }
 
 __global__ void __launch_bounds__(HIST_THREADS)
@@ -306,8 +324,10 @@ hipError_t launch_batch_search_hist(hipStream_t st, int64_t nseg,
                                     unsigned long long *sum, double2 *tlo,
                                     double2 *thi) {
     if (nseg <= 0 || nslots <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_hist, dim3((unsigned)nseg), dim3(LIST_THREADS),
-                       0, st, segs, inst, states, E, A_rel, cnt, sum);
+    hipLaunchKernelGGL(k_batch_hist,
+                       dim3((unsigned)((nseg + BHIST_SEGS - 1) / BHIST_SEGS)),
+                       dim3(LIST_THREADS), 0, st, segs, nseg, inst, states, E,
+                       A_rel, cnt, sum);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_batch_hist_walk, dim3(nslots), dim3(HIST_THREADS), 0,
