@@ -205,6 +205,22 @@ def test_eval_wave_target_changes_speed_only():
     ctx.close()
 
 
+def test_autotuner_times_every_setting():
+    """The autotuner of the many-integral driver runs the workload at every
+    (integrals in flight, wave target) pair, finds no setting that changes
+    a schedule, and returns the fastest row of its table."""
+    _say("autotune")
+    from paper_2104_06494_amd import autotune
+    wl = _small_corner_batch(8, seed=48)
+    out = autotune.tune_batched(wl, count=8, wave_targets=(512, 4096),
+                                slots=(2, 4), reps=1)
+    assert out["B"] == 8
+    assert {(r["slots"], r["wave_target"]) for r in out["table"]} == \
+        {(2, 512), (2, 4096), (4, 512), (4, 4096)}
+    assert all(r["schedule_diffs"] == 0 and r["ms"] > 0 for r in out["table"])
+    assert out["best"]["ms"] == min(r["ms"] for r in out["table"])
+
+
 def test_batch_bitwise_reproducible():
     _say("batch-determinism")
     wl = _small_corner_batch(8, seed=45)
