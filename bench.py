@@ -292,7 +292,8 @@ def batched(args):
     with pg.Context(capacity=slots * wl.max_regions, dim_max=wl.d) as ctx:
         if args.eval_waves:
             ctx.set_eval_waves(args.eval_waves)
-        ctx.integrate_batch_workload(wl, count=min(B, 2 * slots))
+        if not args.no_batch_warmup:
+            ctx.integrate_batch_workload(wl, count=min(B, 2 * slots))
         rb, tb, tbs = _median_runs(lambda: ctx.integrate_batch_workload(wl, count=B),
                                    args.reps)
         fe = sum(r.fevals for r in rb)
@@ -362,7 +363,8 @@ def adjoint(args):
     slots = max(1, min(args.batch_slots // 2, args.adjoint_capacity // wl.max_regions))
     kw = dict(error_rule=args.adjoint_error_rule)
     with pg.Context(capacity=slots * wl.max_regions, dim_max=wl.d) as ctx:
-        ctx.integrate_batch_workload(wl, count=min(B, slots), grad=True, **kw)
+        if not args.no_batch_warmup:
+            ctx.integrate_batch_workload(wl, count=min(B, slots), grad=True, **kw)
         rf, tf, tfs = _median_runs(
             lambda: ctx.integrate_batch_workload(wl, count=B, **kw), args.reps)
         (rg, G, _), tg, tgs = _median_runs(
@@ -663,6 +665,9 @@ def main():
     ap.add_argument("--eval-waves", type=int, default=0,
                     help="EVALUATE's wave target in the batched run (0: the "
                          "library's default)")
+    ap.add_argument("--no-batch-warmup", action="store_true",
+                    help="skip the warm-up of the batched and derivative runs "
+                         "(a kernel trace then covers only the reported runs)")
     ap.add_argument("--batch-slots", type=int, default=64,
                     help="integrals in flight in the batched run (each "
                          "reserves 2^21 regions of workspace)")
