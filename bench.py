@@ -52,7 +52,12 @@ F_FLOP = {("gaussian", 5): 47.0, ("product_peak", 3): 20.0, ("oscillatory", 8): 
 # on (first 16 hex digits of the sha256 of pg_eval_kernels.hpp followed by
 # pg_eval_defs.hpp, comments and blank space removed); reported as null
 # otherwise.
+# The same counter runs give the FP64 operations the kernel executes per
+# evaluation, 64 x (ADD + MUL + TRANS + 2 FMA)_F64 / evaluations: fewer than
+# the algorithmic F + 1, because the kernel shares the unmoved coordinates'
+# terms within a unit and the vertices' per-axis terms within a region.
 EVAL_TRAFFIC = {"bytes_per_launch": 39379407.2, "kernel_sha256": "5e52acb6786c2b51",
+                "fp64_flop_per_eval": 2.8541e10 / 784748322,
                 "profile": "profiles/evaluate_gaussian_d5_counters.txt"}
 # MI355X FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz.
 PEAK_FP64_TFLOPS = 78.6
@@ -186,6 +191,9 @@ def headline(args):
     value = T["fevals"] / T["wall_s"]
     launches = T["launches"]
     achieved = T["alg_flop"] / (T["eval_ms"] * 1e-3) / 1e12
+    key_ok = _kernel_sha() == EVAL_TRAFFIC["kernel_sha256"]
+    executed = (T["regions"] * npts * EVAL_TRAFFIC["fp64_flop_per_eval"]
+                / (T["eval_ms"] * 1e-3) / 1e12) if key_ok else None
     summ = _run_summary(wl, T, exact)
     out = {
         "metric": "FP64 integrand evals/s + time-to-tol at 1e-6; batched & adjoint vs plain, 1 GPU",
@@ -219,8 +227,13 @@ def headline(args):
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS,
-            "traffic": (EVAL_TRAFFIC["bytes_per_launch"]
-                        if _kernel_sha() == EVAL_TRAFFIC["kernel_sha256"] else None),
+            "frac_basis": "algorithmic: evaluations x (F_f + 1) FP64 FLOP",
+            "executed_fp64_frac": (executed / PEAK_FP64_TFLOPS
+                                   if executed is not None else None),
+            "executed_fp64_basis": "FP64 operations the kernel executes per "
+                                   "evaluation, from rocprofv3 counters of this "
+                                   "kernel source",
+            "traffic": EVAL_TRAFFIC["bytes_per_launch"] if key_ok else None,
             "traffic_unit": "HBM bytes per launch",
             "avg_launch_ms": T["eval_ms"] / launches,
             "alg_flop_per_launch": T["alg_flop"] / launches,
