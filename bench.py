@@ -43,10 +43,7 @@ sys.path.insert(0, ROOT)
 # kernel (--mode integrand); see profiles/integrand_flops.txt.
 # Algorithmic FLOP per region = N points x (F + 1 orbit accumulation).
 F_FLOP = {("gaussian", 5): 47.0, ("product_peak", 3): 20.0, ("oscillatory", 8): 73.0,
-          ("corner_peak", 6): 27.0,
-          # not measured: the d=5 Gaussian's counts plus one more axis (one
-          # subtraction, one multiply, one FMA)
-          ("gaussian", 6): 51.0}
+          ("corner_peak", 6): 25.0, ("gaussian", 6): 51.0}
 # HBM bytes per evaluate launch of this workload from FETCH_SIZE / WRITE_SIZE
 # (scaled by a plain copy), valid only for the kernel source they were taken
 # on (first 16 hex digits of the sha256 of pg_eval_kernels.hpp followed by
@@ -600,7 +597,8 @@ def integrand_mode(args):
     torch.cuda.set_device(0)
     wl = {"gaussian_d5": W.gaussian_d5, "product_peak_d3": W.product_peak_d3,
           "oscillatory_d8": lambda: W.oscillatory_d8(1),
-          "corner_peak_d6": lambda: W.corner_peak_batch_d6().instance(0)}[args.integrand]()
+          "corner_peak_d6": lambda: W.corner_peak_batch_d6().instance(0),
+          "gaussian_d6": lambda: W.gaussian_grad_d6().instance(0)}[args.integrand]()
     n = 1 << 22
     x = torch.rand(wl.d, n, dtype=torch.float64, device="cuda")
     with pg.Context(capacity=1 << 10, dim_max=wl.d) as ctx:
@@ -658,7 +656,7 @@ def main():
                     help="integrals per family and tolerance in --mode errors")
     ap.add_argument("--integrand", default="gaussian_d5",
                     choices=["gaussian_d5", "product_peak_d3", "oscillatory_d8",
-                             "corner_peak_d6"],
+                             "corner_peak_d6", "gaussian_d6"],
                     help="integrand of --mode integrand")
     ap.add_argument("--reps", type=int, default=5,
                     help="timed runs of the batched and derivative comparisons "
