@@ -14,8 +14,9 @@ integrals), median of `reps` runs after a warm-up, and returns the fastest.
 The wave target changes the order in which a block's waves add their
 partial sums, so an integral whose classification sits on a rounding tie
 can take another schedule; each row counts the integrals whose schedule
-(status, iterations, regions evaluated) differs from the first setting's. The segment length of the
-list kernels is a compile-time constant and is not tuned here.
+(status, iterations, regions evaluated) differs from the first setting's.
+The segment length of the list kernels is a compile-time constant and is
+not tuned here.
 """
 from __future__ import annotations
 
