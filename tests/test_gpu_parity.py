@@ -109,8 +109,10 @@ def test_peak_reciprocal_to_a_few_ulps(ctx, family, d):
 # EVALUATE
 # ---------------------------------------------------------------------------
 
+# every dimension the kernels are instantiated for (2..10), ragged tails
 CASES = [(fam, d, n) for fam in ("product_peak", "gaussian", "oscillatory", "corner_peak")
-         for d, n in ((2, 1), (3, 65), (5, 1000), (6, 3001), (8, 777))]
+         for d, n in ((2, 1), (3, 65), (4, 130), (5, 1000), (6, 3001), (7, 257),
+                      (8, 777), (9, 65), (10, 129))]
 
 
 @pytest.mark.parametrize("family,d,n", CASES)
@@ -316,7 +318,8 @@ def test_threshold_search_spread(ctx, seed, relax, sigma):
         np.testing.assert_array_equal(A.cpu().numpy(), A_rel)
 
 
-@pytest.mark.parametrize("d,n", [(2, 1), (3, 2049), (5, 4096), (8, 10001)])
+@pytest.mark.parametrize("d,n", [(2, 1), (3, 2049), (4, 700), (5, 4096), (6, 3001),
+                                 (7, 1025), (8, 10001), (9, 129), (10, 5000)])
 def test_filter_split_bit_exact(ctx, d, n):
     _say("filter-split", d, n)
     rng = np.random.default_rng(d * n)
