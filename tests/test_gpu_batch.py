@@ -155,6 +155,26 @@ def test_batch_other_families(family, d, g):
     ctx.close()
 
 
+@pytest.mark.parametrize("d", [2, 4, 7, 9, 10])
+def test_batch_in_every_other_dimension(d):
+    """The dimensions the tests above leave out, so that every batched
+    compaction and per-region-parameter EVALUATE kernel runs: small
+    Gaussian batches, each integral taking its single run's decisions."""
+    _say("batch-dimension", d)
+    B = 4
+    rng = np.random.default_rng(70 + d)
+    a_lo, a_hi = (4.0, 9.0) if d <= 4 else (1.0, 2.5)   # wider peaks in high d
+    P = np.concatenate([rng.uniform(a_lo, a_hi, (B, d)), rng.uniform(0.3, 0.7, (B, d))], 1)
+    tol = 10.0 ** rng.uniform(-4, -3, B)
+    wl = W.BatchWorkload(f"gaussian_batch_d{d}", "gaussian", d, P, tol, np.full(B, 1e-20),
+                         init_splits=2, max_regions=1 << 16)
+    ctx = _ctx(B * wl.max_regions, d)
+    res = ctx.integrate_batch_workload(wl)
+    _check_against_single(ctx, wl, res)
+    assert sum(r.status_name == "OK" for r in res) >= 1
+    ctx.close()
+
+
 def test_batch_against_oracle_directly():
     """Four integrals compared with the oracle's own free run."""
     _say("batch-vs-oracle")
