@@ -66,9 +66,11 @@ def test_integrand_values(ctx, family, d, p):
 
 
 EVAL_CASES = [(fam, d, n, p) for fam in ("c0", "discontinuous")
-              for d, n in ((2, 1), (3, 65), (5, 1000), (6, 3001), (8, 777))
+              for d, n in ((2, 1), (3, 65), (5, 1000), (6, 3001), (8, 777), (9, 65),
+                           (10, 129))
               for p in (None,)] + \
-             [("box", d, n, [pw]) for d, n in ((2, 129), (5, 1000), (8, 777))
+             [("box", d, n, [pw]) for d, n in ((2, 129), (3, 65), (5, 1000), (6, 300),
+                                               (8, 777), (10, 129))
               for pw in (11.0, 7.5, 2.3)]
 
 
